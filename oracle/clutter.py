@@ -1,0 +1,101 @@
+"""SVD clutter filter and power Doppler, FP64 (numpy).
+
+Test infrastructure only.
+
+Post-processing (Section 2.4.2, and the singular-value analyses of Section 3):
+the slow-time ensemble is arranged as a Casorati matrix S (voxels x frames),
+its leading singular components (tissue) are removed, and the power-Doppler
+value of a voxel is the mean over frames of the squared magnitude of what
+remains.
+
+The singular value decomposition of S is taken through its Gram matrix:
+G = S^H S = V diag(lambda) V^H, sigma_k = sqrt(lambda_k) (lambda descending,
+negative round-off clamped to zero).  The filter keeps the orthogonal
+complement of the K leading right singular vectors:
+    S_f = S - (S V_K) V_K^H,   PD[v] = (1/N_t) sum_f |S_f[v, f]|^2.
+The IQ arrays here use the frame-major layout iq[f][v] = S[v, f].
+"""
+from __future__ import annotations
+
+from typing import Tuple
+
+import numpy as np
+
+CHUNK = 1 << 18
+
+
+def gram(iq: np.ndarray) -> np.ndarray:
+    """G = S^H S, complex128 [N_t][N_t]; iq is [N_t][N_v]."""
+    nt, nv = iq.shape
+    G = np.zeros((nt, nt), dtype=np.complex128)
+    for v0 in range(0, nv, CHUNK):
+        X = iq[:, v0:v0 + CHUNK].astype(np.complex128)
+        G += X.conj() @ X.T
+    return G
+
+
+def eig_desc(G: np.ndarray) -> Tuple[np.ndarray, np.ndarray]:
+    """Eigenvalues (descending, clamped at 0) and eigenvectors (columns) of Hermitian G."""
+    lam, V = np.linalg.eigh(G)
+    lam = lam[::-1].copy()
+    V = V[:, ::-1].copy()
+    lam[lam < 0] = 0.0
+    return lam, V
+
+
+def knee_cutoff(lam: np.ndarray) -> int:
+    """Clutter rank from the singular-value curve (the paper marks the cutoff by
+    eye on the first singular values, Section 3.2).  Written as the chord rule:
+    d_k = 10 log10(max(lambda_k, 1e-30 lambda_1)/lambda_1), chord l_k from
+    (1, d_1) to (N, d_N); k* = argmax over k in [2, N/2] of (l_k - d_k), the
+    first index on ties; K = clamp(k* - 1, 1, N/2 - 1)  (k is 1-based)."""
+    lam = np.asarray(lam, dtype=np.float64)
+    N = lam.size
+    if N < 4:
+        return 1
+    l1 = lam[0]
+    if not l1 > 0:
+        return 1
+    d = 10.0 * np.log10(np.maximum(lam, 1e-30 * l1) / l1)
+    k = np.arange(1, N + 1)
+    chord = d[0] + (d[-1] - d[0]) * (k - 1) / (N - 1)
+    gap = chord - d
+    best_k, best = 2, -np.inf
+    for kk in range(2, N // 2 + 1):
+        if gap[kk - 1] > best:
+            best, best_k = gap[kk - 1], kk
+    return int(min(max(best_k - 1, 1), N // 2 - 1))
+
+
+def filter_iq(iq: np.ndarray, V: np.ndarray, K: int) -> np.ndarray:
+    """S_f = S - (S V_K) V_K^H in the frame-major layout: returns complex128 [N_t][N_v]."""
+    nt, nv = iq.shape
+    VK = V[:, :K]
+    out = np.empty((nt, nv), dtype=np.complex128)
+    for v0 in range(0, nv, CHUNK):
+        S = iq[:, v0:v0 + CHUNK].astype(np.complex128).T          # [nv][nt]
+        P = S @ VK                                                 # [nv][K]
+        out[:, v0:v0 + CHUNK] = (S - P @ VK.conj().T).T
+    return out
+
+
+def power_doppler(iq: np.ndarray) -> np.ndarray:
+    """PD[v] = mean_f |iq[f, v]|^2 (float64 [N_v])."""
+    iq = np.asarray(iq)
+    return np.mean(np.abs(iq.astype(np.complex128)) ** 2, axis=0)
+
+
+def svd_filter_pd(iq: np.ndarray, cutoff: int):
+    """Full clutter-filter chain.  cutoff >= 0: fixed K; -1: knee rule.
+    Returns (pd float64 [N_v], lam float64 [N_t], V complex128, K)."""
+    G = gram(iq)
+    lam, V = eig_desc(G)
+    K = knee_cutoff(lam) if cutoff < 0 else int(cutoff)
+    pd = power_doppler(filter_iq(iq, V, K)) if K > 0 else power_doppler(iq)
+    return pd, lam, V, K
+
+
+def projector(V: np.ndarray, K: int) -> np.ndarray:
+    """V_K V_K^H (phase-invariant representation of the tissue subspace)."""
+    VK = V[:, :K]
+    return VK @ VK.conj().T
