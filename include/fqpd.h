@@ -1,0 +1,224 @@
+/*
+ * fqpd.h -- C ABI of the MI355X (gfx950) ultrafast power-Doppler reconstruction path.
+ *
+ * Reconstruction hot path of 3D-FQFlow (arXiv 2509.05464): per-element RF of tilted
+ * plane-wave transmits on a 2-D matrix array -> RF-to-IQ demodulation -> 3-D delay-and-sum
+ * with coherent compounding over transmits (one IQ volume per frame) -> Casorati Gram ->
+ * FP64 Hermitian eigendecomposition and rank selection -> SVD clutter filter -> power
+ * Doppler.  Beside the SVD filter sits a learned slow-time convolutional filter (BF16
+ * training and inference kernels) with the SVD result as its fallback.
+ *
+ * Conventions (all entry points):
+ *  - Array arguments are DEVICE pointers, caller-owned, C-order; complex arrays are
+ *    interleaved (re, im) pairs (layout-compatible with torch.complex64/complex128).
+ *    Parameter structs (fq_probe, fq_tx, fq_grid, fq_pulse) are HOST pointers.
+ *  - Units are SI (m, s, Hz, m/s) and radians.
+ *  - Every call is asynchronous on `stream` (a hipStream_t; NULL = the null stream).
+ *    The library keeps no pointer after return except for work queued on `stream`;
+ *    buffers must stay alive until that work completes.  Hot calls never allocate:
+ *    the caller supplies workspaces whose sizes the *_workspace_size queries return.
+ *  - Return value: FQ_OK or an FQ_E_* status; fq_last_error() gives a thread-local
+ *    message for the last failure.  Outputs are undefined after a failure.  Nothing
+ *    throws or aborts across the ABI.  Numeric failures detected on the device
+ *    (eigensolver non-convergence) are reported through device status words.
+ *  - Pointers must be 16-byte aligned (FQ_E_INVALID otherwise).
+ *
+ * Geometry (shared by every entry point):
+ *  - element e = ix + nx_el*iy sits at ((ix-(nx_el-1)/2) pitch_x, (iy-(ny_el-1)/2) pitch_y, 0);
+ *  - transmit a is a plane wave with direction u_a = (sin tx, sin ty, sqrt(1 - sin^2 tx - sin^2 ty))
+ *    fired so that t = 0 when the first element fires: tau_tx(a, r) = u_a.r/c - min_e u_a.p_e/c;
+ *  - receive delay tau_rx(e, r) = |r - p_e| / c;
+ *  - voxel v = ix + nx*(iy + ny*iz) is centred at (x0 + ix dx, y0 + iy dy, z0 + iz dz).
+ */
+#ifndef FQPD_H
+#define FQPD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FQ_MAX_ANGLES 32
+#define FQ_MAX_NT 512
+
+enum { FQ_OK = 0, FQ_E_INVALID = 1, FQ_E_WORKSPACE = 2, FQ_E_HIP = 3, FQ_E_NUMERIC = 4 };
+enum { FQ_INTERP_LINEAR = 0, FQ_INTERP_HERMITE = 1 };
+enum { FQ_GRAM_FP32 = 0, FQ_GRAM_SPLIT_BF16 = 1, FQ_GRAM_BF16 = 2 };
+
+typedef struct {
+    int32_t nx_el, ny_el;     /* regular matrix array, nx_el*ny_el elements */
+    double pitch_x, pitch_y;  /* element pitch, m */
+    double fc_hz;             /* transmit centre frequency */
+    double fs_hz;             /* RF sampling rate */
+    double c_mps;             /* speed of sound */
+} fq_probe;
+
+typedef struct {
+    int32_t n_angles;                     /* 1..FQ_MAX_ANGLES transmits per frame */
+    double tilt_rad[FQ_MAX_ANGLES][2];    /* (theta_x, theta_y) of each plane wave */
+} fq_tx;
+
+typedef struct {
+    int32_t nx, ny, nz;                   /* voxel counts */
+    double x0, y0, z0;                    /* centre of voxel (0,0,0), m */
+    double dx, dy, dz;                    /* voxel spacing, m */
+} fq_grid;
+
+typedef struct {
+    double n_cycles;      /* Gaussian envelope FWHM in carrier cycles (2) */
+    double trunc_sigmas;  /* pulse support +-trunc_sigmas * sigma (5) */
+    double r_ref_m;       /* reference distance of the 1/r receive amplitude (1e-3) */
+} fq_pulse;
+
+/* ---------------------------------------------------------------------------------
+ * rf_synth -- RF of point scatterers under tilted plane-wave transmits.
+ * Weak scattering / linear superposition (Section 2.3) with the analytic echo of a
+ * point scatterer: a Gaussian-envelope pulse g(t) = exp(-t^2/2s^2) cos(2 pi fc t),
+ * s = n_cycles/(2 sqrt(2 ln 2) fc), zero for |t| > trunc_sigmas*s, delayed by
+ * tau_tx + tau_rx and scaled by amp * r_ref/|r - p_e|:
+ *     rf[f][a][e][n] (+)= sum_s amp[s] (r_ref/rho) g(n/fs - tau_tx(a, r_s(f)) - rho/c).
+ *  pos        float32 [n_frames][n_scat][3] (metres), or [1][n_scat][3] if pos_static;
+ *  pos_static 1: every frame sees the same positions; each trace is synthesised once and
+ *             written to all frames (the static-tissue reuse of Algorithm 1);
+ *  amp        float32 [n_scat] reflectivities;
+ *  accumulate 0: rf is overwritten; 1: the echoes are added to rf (RF_total = RF_phantom +
+ *             RF_flow of Algorithm 1 by two calls);
+ *  rf         float32 [n_frames][n_angles][n_elem][n_samples].
+ *  Errors: FQ_E_INVALID for null pointers, non-positive sizes, n_samples > 8192,
+ *  n_angles*n_samples beyond the on-chip trace budget (40960).  n_scat == 0 is valid.
+ * ------------------------------------------------------------------------------- */
+int rf_synth(const fq_probe* probe, const fq_tx* tx, const fq_pulse* pulse, int32_t n_frames,
+             int64_t n_scat, const float* pos, int32_t pos_static, const float* amp,
+             int32_t n_samples, int32_t accumulate, float* rf, void* stream);
+
+/* ---------------------------------------------------------------------------------
+ * das_beamform -- rf2iq then delay-and-sum with coherent compounding (Section 2.4.1,
+ * Algorithm 3: per-transmit delay application reused for every frame, mean over
+ * transmits, voxels processed independently in chunks).
+ *  rf2iq:  b[n] = 2 sum_{k=-16..16} h_k rf[n-k] exp(-i 2 pi fc (n-k)/fs), rf = 0 outside
+ *          [0, T); h_k = Hann(33) windowed sinc with cutoff fc, unit DC gain.
+ *  DAS:    x = fs (tau_tx(a, r_v) + tau_rx(e, r_v)), n = floor(x), alpha = x - n;
+ *          linear  B = (1-alpha) b[n] + alpha b[n+1];
+ *          hermite B = Catmull-Rom cubic on b[n-1..n+2];  taps outside [0, T) read 0;
+ *          iq[f][v] = (1/A) sum_a sum_e B_{f,a,e} exp(+i 2 pi fc x / fs).
+ *  rf     float32 [n_frames][n_angles][n_elem][n_samples];
+ *  iq     complex64 [n_frames][n_vox] (the Casorati matrix, frame-major);
+ *  ws     device workspace of ws_bytes >= das_workspace_size(..., minimum=1); with
+ *         das_workspace_size(..., minimum=0) bytes all frames are demodulated in one pass,
+ *         otherwise frame blocks are processed in turn (results are identical).
+ *  Errors: FQ_E_INVALID (null/misaligned pointers, bad sizes, unsupported geometry: the
+ *  per-tile delay window must fit on chip), FQ_E_WORKSPACE (ws too small).
+ * ------------------------------------------------------------------------------- */
+size_t das_workspace_size(const fq_probe* probe, const fq_tx* tx, int32_t n_frames,
+                          int32_t n_samples, int32_t minimum);
+int das_beamform(const fq_probe* probe, const fq_tx* tx, const fq_grid* grid, int32_t n_frames,
+                 int32_t n_samples, const float* rf, int32_t interp, void* ws, size_t ws_bytes,
+                 float* iq, void* stream);
+
+/* ---------------------------------------------------------------------------------
+ * casorati_gram -- G = S^H S for the Casorati matrix S[v][f] = iq[f][v] (Section 2.4.2:
+ * the SVD clutter filter works on S; its right singular vectors and squared singular
+ * values are the eigenpairs of G).
+ *  gram_mode FQ_GRAM_FP32:       FP32 matrix-core products, FP32 accumulation within voxel
+ *                                blocks, FP64 accumulation across blocks;
+ *            FQ_GRAM_SPLIT_BF16: each FP32 operand split as hi = bf16(x), lo = bf16(x - hi);
+ *                                three BF16 matrix-core products hi*hi + hi*lo + lo*hi, FP32
+ *                                accumulation, FP64 across blocks;
+ *            FQ_GRAM_BF16:       hi*hi only (negative control).
+ *  iq    complex64 [n_t][n_vox];  gram complex128 [n_t][n_t] (full Hermitian matrix).
+ *  Errors: FQ_E_INVALID (n_t < 1 or > FQ_MAX_NT, n_vox < 1), FQ_E_WORKSPACE.
+ * ------------------------------------------------------------------------------- */
+size_t gram_workspace_size(int64_t n_vox, int32_t n_t, int32_t gram_mode);
+int casorati_gram(const float* iq, int64_t n_vox, int32_t n_t, int32_t gram_mode, void* ws,
+                  size_t ws_bytes, double* gram, void* stream);
+
+/* ---------------------------------------------------------------------------------
+ * svd_clutter_filter -- eigendecomposition of G in FP64 on the GPU (cyclic Jacobi),
+ * rank selection, projection and power Doppler (Section 2.4.2; Section 3.2 marks the
+ * cutoff on the singular-value curve).
+ *  cutoff >= 0: K = cutoff; cutoff == -1: knee rule on the dB spectrum
+ *     d_k = 10 log10(max(l_k, 1e-30 l_1)/l_1), chord l from (1, d_1) to (N, d_N),
+ *     k* = argmax_{k in [2, N/2]} (chord_k - d_k) (first on ties), K = clamp(k*-1, 1, N/2-1).
+ *  S_f = S - (S V_K) V_K^H (explicit subtraction);  pd[v] = (1/N_t) sum_f |S_f[v][f]|^2.
+ *  iq       complex64 [n_t][n_vox];  gram complex128 [n_t][n_t] from casorati_gram;
+ *  iq_filt  complex64 [n_t][n_vox] or NULL;  pd float32 [n_vox] or NULL;
+ *  sigma    float64 [n_t] singular values, descending (device);
+ *  k_used   int32 [1] (device): the K applied;
+ *  status   int32 [1] (device) or NULL: 0 ok, FQ_E_NUMERIC if the eigensolver did not
+ *           converge (results are then those of the last sweep).
+ *  K is limited to 64 (FQ_E_INVALID for a larger fixed cutoff; the knee result is
+ *  clamped to 64 and the status word set to FQ_E_NUMERIC).
+ * ------------------------------------------------------------------------------- */
+size_t svd_workspace_size(int64_t n_vox, int32_t n_t);
+int svd_clutter_filter(const float* iq, int64_t n_vox, int32_t n_t, const double* gram,
+                       int32_t cutoff, void* ws, size_t ws_bytes, float* iq_filt, float* pd,
+                       double* sigma, int32_t* k_used, int32_t* status, void* stream);
+
+/* eigendecomposition only: lam float64 [n_t] descending (clamped >= 0), vecs complex128
+ * [n_t][n_t] with column k the eigenvector of lam[k].  Same workspace as above. */
+int hermitian_eig(const double* gram, int32_t n_t, void* ws, size_t ws_bytes, double* lam,
+                  double* vecs, int32_t* status, void* stream);
+
+/* ---------------------------------------------------------------------------------
+ * power_doppler -- pd[v] = (1/n_t) sum_f |iq[f][v]|^2 (Section 2.4.2 power Doppler map).
+ *  iq complex64 [n_t][n_vox]; pd float32 [n_vox].
+ * ------------------------------------------------------------------------------- */
+int power_doppler(const float* iq, int64_t n_vox, int32_t n_t, float* pd, void* stream);
+
+/* ---------------------------------------------------------------------------------
+ * Learned slow-time clutter filter.  Per voxel series s = iq[:, v]:
+ *   x = [Re, Im](s) / r,  r = sqrt(mean_f |s_f|^2 + eps);
+ *   h1 = GELU(conv9(x; W1[32][2][9], b1)), h2 = GELU(conv9(h1; W2[32][32][9], b2)),
+ *   h3 = GELU(conv9(h2; W3[32][32][9], b3)), y = W4[2][32] h3 + b4;
+ *   conv9(z)[o][t] = b[o] + sum_i sum_{k<9} W[o][i][k] z[i][t+k-4] (zeros outside [0, T));
+ *   GELU(z) = z/2 (1 + erf(z/sqrt 2)); blood estimate s_b = r (y0 + i y1).
+ * Parameter vector (19170 entries): W1 | b1 | W2 | b2 | W3 | b3 | W4 | b4 (row-major).
+ * Weights are used in BF16 (w_bf16, RNE copies kept by lcf_adam_step), biases in FP32
+ * (w), activations are stored in BF16, every accumulation is FP32.
+ * ------------------------------------------------------------------------------- */
+#define LCF_N_PARAM 19170
+/* act workspace bytes for training on n_series series of n_t frames */
+size_t lcf_act_size(int64_t n_series, int32_t n_t);
+
+/*  x      complex64 [n_t][n_series] (frame-major, like iq);
+ *  act    bf16 activation store of lcf_act_size bytes, or NULL (inference);
+ *  y      complex64 [n_t][n_series] blood estimate, or NULL;
+ *  pd     float32 [n_series] power Doppler of the estimate, or NULL. */
+int lcf_forward(const float* w, const uint16_t* w_bf16, const float* x, int64_t n_series,
+                int32_t n_t, float eps, uint16_t* act, float* y, float* pd, void* stream);
+
+/*  After lcf_forward(..., act, ...) on the same x: gradient of
+ *  loss = mean over (series, channel, t) of (y - [Re, Im](target)/r)^2.
+ *  grad float32 [19170] (overwritten); loss float32 [1] (device, overwritten). */
+int lcf_backward(const float* w, const uint16_t* w_bf16, const float* x, const float* target,
+                 int64_t n_series, int32_t n_t, float eps, const uint16_t* act, float* grad,
+                 float* loss, void* stream);
+
+/*  Adam with bias correction on FP32 master weights; refreshes the BF16 copy.
+ *  step is 1-based. */
+int lcf_adam_step(float* w, uint16_t* w_bf16, float* m, float* v, const float* grad,
+                  int32_t n_param, float lr, float beta1, float beta2, float eps, int32_t step,
+                  void* stream);
+
+/*  Gather training series: dst[t][b] = src[idx[b] / n_vox][t][idx[b] % n_vox]
+ *  (src complex64 [n_vol][n_t][n_vox]; idx int64 [batch], device). */
+int lcf_gather(const float* src, int64_t n_vox, int32_t n_t, int64_t n_vol, const int64_t* idx,
+               int64_t batch, float* dst, void* stream);
+
+/*  SVD fallback judge: D = 10 log10(sum (pd_l - pd_s)^2 / sum pd_s^2).  If D > tau_db or
+ *  pd_l holds a non-finite value, out = pd_s and flag = 1; otherwise out = pd_l, flag = 0.
+ *  d_db float32 [1] receives D (device).  ws >= fallback_workspace_size(n). */
+size_t fallback_workspace_size(int64_t n);
+int lcf_fallback(const float* pd_l, const float* pd_s, int64_t n, float tau_db, void* ws,
+                 size_t ws_bytes, float* out, int32_t* flag, float* d_db, void* stream);
+
+/* Library identification and the thread-local message of the last failure. */
+int fq_version(void);
+const char* fq_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FQPD_H */

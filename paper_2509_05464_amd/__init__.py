@@ -1,0 +1,17 @@
+"""MI355X (gfx950) ultrafast power-Doppler reconstruction path.
+
+RF synthesis -> RF-to-IQ + 3-D delay-and-sum with coherent compounding -> Casorati
+Gram -> FP64 eigendecomposition and rank selection -> SVD clutter filter -> power
+Doppler, plus a learned slow-time convolutional clutter filter with SVD fallback.
+All stages are hand-written HIP kernels in libfqpd.so (C ABI: include/fqpd.h);
+this package is the thin Python binding over it.
+"""
+from ._lib import (  # noqa: F401
+    FQ_MAX_ANGLES, FQ_MAX_NT, LCF_N_PARAM, FqError,
+    GRAM_FP32, GRAM_SPLIT_BF16, GRAM_BF16, INTERP_LINEAR, INTERP_HERMITE,
+    Probe, Tx, Grid, Pulse, make_probe, make_tx, make_grid, make_pulse, lib,
+    rf_synth, das_workspace_size, das_beamform, gram_workspace_size, casorati_gram,
+    svd_workspace_size, svd_clutter_filter, hermitian_eig, power_doppler,
+    lcf_act_size, lcf_forward, lcf_backward, lcf_adam_step, lcf_gather,
+    fallback_workspace_size, lcf_fallback,
+)

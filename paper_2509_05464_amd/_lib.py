@@ -1,0 +1,252 @@
+"""ctypes binding of libfqpd.so (the C ABI in include/fqpd.h).
+
+Argument marshalling only: every entry point takes torch tensors that already live
+on the GPU, passes their device pointers and the current HIP stream, and raises
+FqError when the library returns a non-OK status.  All arithmetic runs in the HIP
+kernels; there is no CPU fallback.  The library must have been built in-tree
+(paper_2509_05464_amd.build.build()); loading fails loudly otherwise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence, Tuple
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, 'libfqpd.so')
+
+FQ_MAX_ANGLES = 32
+FQ_MAX_NT = 512
+LCF_N_PARAM = 19170
+FQ_OK, FQ_E_INVALID, FQ_E_WORKSPACE, FQ_E_HIP, FQ_E_NUMERIC = range(5)
+INTERP_LINEAR, INTERP_HERMITE = 0, 1
+GRAM_FP32, GRAM_SPLIT_BF16, GRAM_BF16 = 0, 1, 2
+
+
+class FqError(RuntimeError):
+    def __init__(self, fn: str, status: int, msg: str):
+        super().__init__(f'{fn} failed with status {status}: {msg}')
+        self.status = status
+
+
+class Probe(ctypes.Structure):
+    _fields_ = [('nx_el', ctypes.c_int32), ('ny_el', ctypes.c_int32),
+                ('pitch_x', ctypes.c_double), ('pitch_y', ctypes.c_double),
+                ('fc_hz', ctypes.c_double), ('fs_hz', ctypes.c_double), ('c_mps', ctypes.c_double)]
+
+
+class Tx(ctypes.Structure):
+    _fields_ = [('n_angles', ctypes.c_int32), ('tilt_rad', (ctypes.c_double * 2) * FQ_MAX_ANGLES)]
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [('nx', ctypes.c_int32), ('ny', ctypes.c_int32), ('nz', ctypes.c_int32),
+                ('x0', ctypes.c_double), ('y0', ctypes.c_double), ('z0', ctypes.c_double),
+                ('dx', ctypes.c_double), ('dy', ctypes.c_double), ('dz', ctypes.c_double)]
+
+
+class Pulse(ctypes.Structure):
+    _fields_ = [('n_cycles', ctypes.c_double), ('trunc_sigmas', ctypes.c_double), ('r_ref_m', ctypes.c_double)]
+
+
+def make_probe(nx_el, ny_el, pitch_x, pitch_y, fc, fs, c) -> Probe:
+    return Probe(nx_el, ny_el, pitch_x, pitch_y, fc, fs, c)
+
+
+def make_tx(tilts_rad: Sequence[Tuple[float, float]]) -> Tx:
+    t = Tx()
+    if not 1 <= len(tilts_rad) <= FQ_MAX_ANGLES:
+        raise ValueError('1..32 transmits')
+    t.n_angles = len(tilts_rad)
+    for i, (a, b) in enumerate(tilts_rad):
+        t.tilt_rad[i][0] = a
+        t.tilt_rad[i][1] = b
+    return t
+
+
+def make_grid(nx, ny, nz, x0, y0, z0, dx, dy, dz) -> Grid:
+    return Grid(nx, ny, nz, x0, y0, z0, dx, dy, dz)
+
+
+def make_pulse(n_cycles=2.0, trunc_sigmas=5.0, r_ref=1e-3) -> Pulse:
+    return Pulse(n_cycles, trunc_sigmas, r_ref)
+
+
+_lib: Optional[ctypes.CDLL] = None
+
+_P = ctypes.POINTER
+_vp, _i32, _i64, _f32, _sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_float, ctypes.c_size_t
+
+_SIGS = {
+    'rf_synth': (ctypes.c_int, [_P(Probe), _P(Tx), _P(Pulse), _i32, _i64, _vp, _i32, _vp, _i32, _i32, _vp, _vp]),
+    'das_workspace_size': (_sz, [_P(Probe), _P(Tx), _i32, _i32, _i32]),
+    'das_beamform': (ctypes.c_int, [_P(Probe), _P(Tx), _P(Grid), _i32, _i32, _vp, _i32, _vp, _sz, _vp, _vp]),
+    'gram_workspace_size': (_sz, [_i64, _i32, _i32]),
+    'casorati_gram': (ctypes.c_int, [_vp, _i64, _i32, _i32, _vp, _sz, _vp, _vp]),
+    'svd_workspace_size': (_sz, [_i64, _i32]),
+    'svd_clutter_filter': (ctypes.c_int, [_vp, _i64, _i32, _vp, _i32, _vp, _sz, _vp, _vp, _vp, _vp, _vp, _vp]),
+    'hermitian_eig': (ctypes.c_int, [_vp, _i32, _vp, _sz, _vp, _vp, _vp, _vp]),
+    'power_doppler': (ctypes.c_int, [_vp, _i64, _i32, _vp, _vp]),
+    'lcf_act_size': (_sz, [_i64, _i32]),
+    'lcf_forward': (ctypes.c_int, [_vp, _vp, _vp, _i64, _i32, _f32, _vp, _vp, _vp, _vp]),
+    'lcf_backward': (ctypes.c_int, [_vp, _vp, _vp, _vp, _i64, _i32, _f32, _vp, _vp, _vp, _vp]),
+    'lcf_adam_step': (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _i32, _f32, _f32, _f32, _f32, _i32, _vp]),
+    'lcf_gather': (ctypes.c_int, [_vp, _i64, _i32, _i64, _vp, _i64, _vp, _vp]),
+    'fallback_workspace_size': (_sz, [_i64]),
+    'lcf_fallback': (ctypes.c_int, [_vp, _vp, _i64, _f32, _vp, _sz, _vp, _vp, _vp, _vp]),
+    'fq_version': (ctypes.c_int, []),
+    'fq_last_error': (ctypes.c_char_p, []),
+}
+
+
+def lib() -> ctypes.CDLL:
+    """Load the in-tree libfqpd.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f'{LIB_PATH} is missing: build it with paper_2509_05464_amd.build.build()')
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _stream() -> int:
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError('expected a GPU tensor')
+    if not t.is_contiguous():
+        raise ValueError('expected a contiguous tensor')
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _check(name: str, st: int):
+    if st != FQ_OK:
+        raise FqError(name, st, lib().fq_last_error().decode())
+
+
+def _f32view(t: torch.Tensor) -> torch.Tensor:
+    return torch.view_as_real(t) if t.is_complex() else t
+
+
+# ----------------------------------------------------------------------------- stages
+def rf_synth(probe: Probe, tx: Tx, pulse: Pulse, pos: torch.Tensor, amp: torch.Tensor, rf: torch.Tensor,
+             pos_static: bool = False, accumulate: bool = False) -> None:
+    """rf float32 [F][A][E][T]; pos float32 [F or 1][S][3]; amp float32 [S]."""
+    F, A, E, T = rf.shape
+    S = amp.numel()
+    st = lib().rf_synth(ctypes.byref(probe), ctypes.byref(tx), ctypes.byref(pulse), F, S, _ptr(pos),
+                        int(pos_static), _ptr(amp), T, int(accumulate), _ptr(rf), _stream())
+    _check('rf_synth', st)
+
+
+def das_workspace_size(probe: Probe, tx: Tx, n_frames: int, n_samples: int, minimum: bool = False) -> int:
+    return lib().das_workspace_size(ctypes.byref(probe), ctypes.byref(tx), n_frames, n_samples, int(minimum))
+
+
+def das_beamform(probe: Probe, tx: Tx, grid: Grid, rf: torch.Tensor, iq: torch.Tensor, ws: torch.Tensor,
+                 interp: int = INTERP_LINEAR) -> None:
+    """rf float32 [F][A][E][T] -> iq complex64 [F][Nv]."""
+    F, A, E, T = rf.shape
+    st = lib().das_beamform(ctypes.byref(probe), ctypes.byref(tx), ctypes.byref(grid), F, T, _ptr(rf), interp,
+                            _ptr(ws), ws.numel() * ws.element_size(), _ptr(_f32view(iq)), _stream())
+    _check('das_beamform', st)
+
+
+def gram_workspace_size(n_vox: int, n_t: int, mode: int = GRAM_FP32) -> int:
+    return lib().gram_workspace_size(n_vox, n_t, mode)
+
+
+def casorati_gram(iq: torch.Tensor, gram: torch.Tensor, ws: torch.Tensor, mode: int = GRAM_FP32) -> None:
+    """iq complex64 [Nt][Nv] -> gram complex128 [Nt][Nt]."""
+    nt, nv = iq.shape
+    st = lib().casorati_gram(_ptr(_f32view(iq)), nv, nt, mode, _ptr(ws), ws.numel() * ws.element_size(),
+                             _ptr(_f32view(gram)), _stream())
+    _check('casorati_gram', st)
+
+
+def svd_workspace_size(n_vox: int, n_t: int) -> int:
+    return lib().svd_workspace_size(n_vox, n_t)
+
+
+def svd_clutter_filter(iq: torch.Tensor, gram: torch.Tensor, ws: torch.Tensor, sigma: torch.Tensor,
+                       k_used: torch.Tensor, cutoff: int = -1, iq_filt: Optional[torch.Tensor] = None,
+                       pd: Optional[torch.Tensor] = None, status: Optional[torch.Tensor] = None) -> None:
+    nt, nv = iq.shape
+    st = lib().svd_clutter_filter(_ptr(_f32view(iq)), nv, nt, _ptr(_f32view(gram)), cutoff, _ptr(ws),
+                                  ws.numel() * ws.element_size(),
+                                  _ptr(_f32view(iq_filt)) if iq_filt is not None else None,
+                                  _ptr(pd), _ptr(sigma), _ptr(k_used), _ptr(status), _stream())
+    _check('svd_clutter_filter', st)
+
+
+def hermitian_eig(gram: torch.Tensor, ws: torch.Tensor, lam: torch.Tensor, vecs: Optional[torch.Tensor] = None,
+                  status: Optional[torch.Tensor] = None) -> None:
+    nt = gram.shape[0]
+    st = lib().hermitian_eig(_ptr(_f32view(gram)), nt, _ptr(ws), ws.numel() * ws.element_size(), _ptr(lam),
+                             _ptr(_f32view(vecs)) if vecs is not None else None, _ptr(status), _stream())
+    _check('hermitian_eig', st)
+
+
+def power_doppler(iq: torch.Tensor, pd: torch.Tensor) -> None:
+    nt, nv = iq.shape
+    st = lib().power_doppler(_ptr(_f32view(iq)), nv, nt, _ptr(pd), _stream())
+    _check('power_doppler', st)
+
+
+# ----------------------------------------------------------------------------- learned filter
+def lcf_act_size(n_series: int, n_t: int) -> int:
+    return lib().lcf_act_size(n_series, n_t)
+
+
+def lcf_forward(w: torch.Tensor, w_bf16: torch.Tensor, x: torch.Tensor, eps: float = 1e-30,
+                act: Optional[torch.Tensor] = None, y: Optional[torch.Tensor] = None,
+                pd: Optional[torch.Tensor] = None) -> None:
+    nt, n = x.shape
+    st = lib().lcf_forward(_ptr(w), _ptr(w_bf16), _ptr(_f32view(x)), n, nt, eps, _ptr(act),
+                           _ptr(_f32view(y)) if y is not None else None, _ptr(pd), _stream())
+    _check('lcf_forward', st)
+
+
+def lcf_backward(w: torch.Tensor, w_bf16: torch.Tensor, x: torch.Tensor, target: torch.Tensor, act: torch.Tensor,
+                 grad: torch.Tensor, loss: torch.Tensor, eps: float = 1e-30) -> None:
+    nt, n = x.shape
+    st = lib().lcf_backward(_ptr(w), _ptr(w_bf16), _ptr(_f32view(x)), _ptr(_f32view(target)), n, nt, eps,
+                            _ptr(act), _ptr(grad), _ptr(loss), _stream())
+    _check('lcf_backward', st)
+
+
+def lcf_adam_step(w: torch.Tensor, w_bf16: torch.Tensor, m: torch.Tensor, v: torch.Tensor, grad: torch.Tensor,
+                  step: int, lr: float = 1e-3, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8) -> None:
+    st = lib().lcf_adam_step(_ptr(w), _ptr(w_bf16), _ptr(m), _ptr(v), _ptr(grad), w.numel(), lr, beta1, beta2, eps,
+                             step, _stream())
+    _check('lcf_adam_step', st)
+
+
+def lcf_gather(src: torch.Tensor, idx: torch.Tensor, dst: torch.Tensor) -> None:
+    """src complex64 [n_vol][Nt][Nv], idx int64 [B] -> dst complex64 [Nt][B]."""
+    n_vol, nt, nv = src.shape
+    st = lib().lcf_gather(_ptr(_f32view(src)), nv, nt, n_vol, _ptr(idx), idx.numel(), _ptr(_f32view(dst)),
+                          _stream())
+    _check('lcf_gather', st)
+
+
+def fallback_workspace_size(n: int) -> int:
+    return lib().fallback_workspace_size(n)
+
+
+def lcf_fallback(pd_l: torch.Tensor, pd_s: torch.Tensor, out: torch.Tensor, flag: torch.Tensor, d_db: torch.Tensor,
+                 ws: torch.Tensor, tau_db: float = -10.0) -> None:
+    st = lib().lcf_fallback(_ptr(pd_l), _ptr(pd_s), pd_l.numel(), tau_db, _ptr(ws), ws.numel() * ws.element_size(),
+                            _ptr(out), _ptr(flag), _ptr(d_db), _stream())
+    _check('lcf_fallback', st)

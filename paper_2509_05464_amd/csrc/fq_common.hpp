@@ -1,0 +1,103 @@
+// Shared host/device helpers of the gfx950 power-Doppler library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+
+#include "../../include/fqpd.h"
+
+namespace fq {
+
+// ------------------------------------------------------------------ errors
+void set_error(const char* fmt, ...);
+int zero_async(void* p, size_t n_bytes, hipStream_t s);
+
+#define FQ_REQUIRE(cond, ...)                         \
+    do {                                              \
+        if (!(cond)) {                                \
+            ::fq::set_error(__VA_ARGS__);             \
+            return FQ_E_INVALID;                      \
+        }                                             \
+    } while (0)
+
+#define FQ_HIP(call)                                                                  \
+    do {                                                                              \
+        hipError_t e_ = (call);                                                       \
+        if (e_ != hipSuccess) {                                                       \
+            ::fq::set_error("%s failed: %s", #call, hipGetErrorString(e_));           \
+            return FQ_E_HIP;                                                          \
+        }                                                                             \
+    } while (0)
+
+#define FQ_LAUNCH_CHECK()                                                             \
+    do {                                                                              \
+        hipError_t e_ = hipGetLastError();                                            \
+        if (e_ != hipSuccess) {                                                       \
+            ::fq::set_error("kernel launch failed: %s", hipGetErrorString(e_));       \
+            return FQ_E_HIP;                                                          \
+        }                                                                             \
+    } while (0)
+
+inline bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+inline size_t round_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// ------------------------------------------------------------------ geometry (host, FP64)
+struct TxHost {
+    int n;
+    double ux[FQ_MAX_ANGLES], uy[FQ_MAX_ANGLES], uz[FQ_MAX_ANGLES];
+    double t0[FQ_MAX_ANGLES];  // min over elements of u.p/c
+};
+
+// u_a and t0_a = min_e (u_a . p_e)/c.  u.p is linear in the element position, so its
+// minimum over the regular array is reached at one of the four corner elements.
+inline TxHost make_tx(const fq_probe& p, const fq_tx& t) {
+    TxHost h{};
+    h.n = t.n_angles;
+    const double hx = 0.5 * (p.nx_el - 1) * p.pitch_x, hy = 0.5 * (p.ny_el - 1) * p.pitch_y;
+    for (int a = 0; a < t.n_angles; ++a) {
+        double sx = std::sin(t.tilt_rad[a][0]), sy = std::sin(t.tilt_rad[a][1]);
+        h.ux[a] = sx;
+        h.uy[a] = sy;
+        h.uz[a] = std::sqrt(1.0 - sx * sx - sy * sy);
+        h.t0[a] = (-std::fabs(sx) * hx - std::fabs(sy) * hy) / p.c_mps;
+    }
+    return h;
+}
+
+inline int check_probe_tx(const fq_probe* p, const fq_tx* t) {
+    FQ_REQUIRE(p && t, "probe/tx must not be NULL");
+    FQ_REQUIRE(p->nx_el > 0 && p->ny_el > 0 && p->nx_el * p->ny_el <= 65536, "bad element counts");
+    FQ_REQUIRE(p->fs_hz > 0 && p->fc_hz > 0 && p->c_mps > 0 && p->fc_hz < 0.5 * p->fs_hz,
+               "need fs > 2 fc > 0 and c > 0");
+    FQ_REQUIRE(t->n_angles >= 1 && t->n_angles <= FQ_MAX_ANGLES, "n_angles must be 1..%d", FQ_MAX_ANGLES);
+    for (int a = 0; a < t->n_angles; ++a) {
+        double sx = std::sin(t->tilt_rad[a][0]), sy = std::sin(t->tilt_rad[a][1]);
+        FQ_REQUIRE(sx * sx + sy * sy < 0.99, "transmit %d: tilt too large", a);
+    }
+    return FQ_OK;
+}
+
+// ------------------------------------------------------------------ device helpers
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// exp(i 2 pi frac) for the fractional part of a double-precision cycle count; the
+// integer part is removed exactly in FP64 and the remainder is evaluated in FP32.
+__device__ __forceinline__ float2 cis_cycles(double cyc) {
+    double fr = cyc - floor(cyc);
+    float s, c;
+    sincospif(2.0f * (float)fr, &s, &c);
+    return make_float2(c, s);
+}
+
+}  // namespace fq

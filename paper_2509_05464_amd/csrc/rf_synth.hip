@@ -1,0 +1,162 @@
+// rf_synth: analytic RF of point scatterers under tilted plane-wave transmits (gfx950).
+//
+// One workgroup owns the traces of one receive element for one frame and a group of
+// transmit angles, held in LDS.  Threads stride over the scatterers; each computes the
+// receive distance once in FP64 (shared by all angles of the group), then for every
+// angle the two-way delay x (samples, FP64) and adds the truncated Gaussian pulse into
+// the LDS trace with float atomics.  The pulse samples use two exact recurrences on
+// the integer sample grid u_k = n0 + k - x:
+//   Gaussian:  G_{k+1} = G_k R_k,  R_{k+1} = R_k Q,  Q = exp(-1/s^2)   (s in samples)
+//   carrier :  C_{k+1} = 2 cos(theta) C_k - C_{k-1},  theta = 2 pi fc/fs
+// so each sample costs one fused multiply-add, three multiplies and one LDS atomic.
+// The whole trace is then written (or added) to global memory once, and for static
+// scatterers to every frame (Algorithm 1 reuses the static tissue RF for all frames).
+#include "fq_common.hpp"
+
+namespace fq {
+namespace {
+
+constexpr int RF_THREADS = 256;
+constexpr int RF_LDS_FLOATS = 16384;  // per-workgroup trace budget (64 KiB)
+
+struct RfArgs {
+    const float* pos;
+    const float* amp;
+    float* rf;
+    int64_t n_scat;
+    int n_frames, n_angles, n_elem, T;
+    int nx_el;
+    int ang0, n_ang;        // angle group of this launch
+    int accumulate;
+    double pitch_x, pitch_y, hx, hy;
+    double fs_c;            // fs / c (samples per metre)
+    double half;            // pulse half-support, samples
+    float inv2s2;           // 1 / (2 s^2), s in samples
+    float q;                // exp(-1 / s^2)
+    float theta;            // 2 pi fc / fs
+    float two_cos_theta;
+    float r_ref;
+    double ux[FQ_MAX_ANGLES], uy[FQ_MAX_ANGLES], uz[FQ_MAX_ANGLES], t0s[FQ_MAX_ANGLES];  // t0s = t0 * fs
+};
+
+template <bool STATIC>
+__global__ void __launch_bounds__(RF_THREADS) rf_synth_kernel(const RfArgs a) {
+    extern __shared__ float tr[];  // [n_ang][T]
+    const int e = blockIdx.x;
+    const int f = STATIC ? 0 : blockIdx.y;
+    const int ntr = a.n_ang * a.T;
+    for (int i = threadIdx.x; i < ntr; i += RF_THREADS) tr[i] = 0.0f;
+    __syncthreads();
+
+    const double pex = ((e % a.nx_el) - 0.5 * (a.nx_el - 1)) * a.pitch_x;
+    const double pey = ((e / a.nx_el) - 0.5 * ((a.n_elem / a.nx_el) - 1)) * a.pitch_y;
+    const float* posf = a.pos + (STATIC ? 0 : (int64_t)f * a.n_scat * 3);
+
+    for (int64_t s = threadIdx.x; s < a.n_scat; s += RF_THREADS) {
+        const double px = posf[3 * s], py = posf[3 * s + 1], pz = posf[3 * s + 2];
+        const double dx = px - pex, dy = py - pey;
+        const double rho = sqrt(dx * dx + dy * dy + pz * pz);
+        const double xrx = rho * a.fs_c;
+        const float scale = (float)((double)a.amp[s] * a.r_ref / rho);
+        for (int j = 0; j < a.n_ang; ++j) {
+            const int an = a.ang0 + j;
+            const double x = (a.ux[an] * px + a.uy[an] * py + a.uz[an] * pz) * a.fs_c - a.t0s[an] + xrx;
+            const double lo = ceil(x - a.half), hi = floor(x + a.half);
+            const int n0 = (int)lo;
+            const int cnt = (int)(hi - lo) + 1;
+            const float u0 = (float)(lo - x);
+            float g = scale * __expf(-u0 * u0 * a.inv2s2);
+            float r = __expf(-(2.0f * u0 + 1.0f) * a.inv2s2);
+            float c0 = cosf(a.theta * u0);
+            float cm = cosf(a.theta * (u0 - 1.0f));
+            float* t = tr + j * a.T;
+            for (int k = 0; k < cnt; ++k) {
+                const int n = n0 + k;
+                if ((unsigned)n < (unsigned)a.T) atomicAdd(&t[n], g * c0);
+                const float cn = a.two_cos_theta * c0 - cm;
+                cm = c0;
+                c0 = cn;
+                g *= r;
+                r *= a.q;
+            }
+        }
+    }
+    __syncthreads();
+
+    const int nf = STATIC ? a.n_frames : 1;
+    for (int ff = 0; ff < nf; ++ff) {
+        const int fo = STATIC ? ff : f;
+        for (int i = threadIdx.x; i < ntr; i += RF_THREADS) {
+            const int j = i / a.T, n = i - j * a.T;
+            const int64_t o = (((int64_t)fo * a.n_angles + a.ang0 + j) * a.n_elem + e) * a.T + n;
+            a.rf[o] = a.accumulate ? a.rf[o] + tr[i] : tr[i];
+        }
+    }
+}
+
+}  // namespace
+}  // namespace fq
+
+using namespace fq;
+
+extern "C" int rf_synth(const fq_probe* probe, const fq_tx* tx, const fq_pulse* pulse, int32_t n_frames,
+                        int64_t n_scat, const float* pos, int32_t pos_static, const float* amp,
+                        int32_t n_samples, int32_t accumulate, float* rf, void* stream) {
+    int st = check_probe_tx(probe, tx);
+    if (st != FQ_OK) return st;
+    FQ_REQUIRE(pulse != nullptr, "pulse must not be NULL");
+    FQ_REQUIRE(pulse->n_cycles > 0 && pulse->trunc_sigmas > 0 && pulse->trunc_sigmas <= 8 && pulse->r_ref_m > 0,
+               "bad pulse parameters");
+    FQ_REQUIRE(n_frames >= 1 && n_samples >= 1 && n_samples <= 8192, "bad n_frames / n_samples");
+    FQ_REQUIRE(n_scat >= 0, "n_scat must be >= 0");
+    FQ_REQUIRE(rf != nullptr && aligned16(rf), "rf must be a 16-byte aligned device pointer");
+    FQ_REQUIRE(n_scat == 0 || (pos && amp), "pos/amp must not be NULL");
+    FQ_REQUIRE(n_samples <= RF_LDS_FLOATS, "n_samples too large");
+    const int E = probe->nx_el * probe->ny_el;
+    const int A = tx->n_angles;
+    hipStream_t s = as_stream(stream);
+    if (n_scat == 0) {
+        return accumulate ? FQ_OK : zero_async(rf, sizeof(float) * (size_t)n_frames * A * E * n_samples, s);
+    }
+    TxHost th = make_tx(*probe, *tx);
+    RfArgs a{};
+    a.pos = pos;
+    a.amp = amp;
+    a.rf = rf;
+    a.n_scat = n_scat;
+    a.n_frames = n_frames;
+    a.n_angles = A;
+    a.n_elem = E;
+    a.T = n_samples;
+    a.nx_el = probe->nx_el;
+    a.accumulate = accumulate ? 1 : 0;
+    a.pitch_x = probe->pitch_x;
+    a.pitch_y = probe->pitch_y;
+    a.fs_c = probe->fs_hz / probe->c_mps;
+    const double sig = pulse->n_cycles / (2.0 * std::sqrt(2.0 * std::log(2.0)) * probe->fc_hz) * probe->fs_hz;
+    a.half = pulse->trunc_sigmas * sig;
+    a.inv2s2 = (float)(1.0 / (2.0 * sig * sig));
+    a.q = (float)std::exp(-1.0 / (sig * sig));
+    a.theta = (float)(2.0 * M_PI * probe->fc_hz / probe->fs_hz);
+    a.two_cos_theta = (float)(2.0 * std::cos(2.0 * M_PI * probe->fc_hz / probe->fs_hz));
+    a.r_ref = (float)pulse->r_ref_m;
+    for (int i = 0; i < A; ++i) {
+        a.ux[i] = th.ux[i];
+        a.uy[i] = th.uy[i];
+        a.uz[i] = th.uz[i];
+        a.t0s[i] = th.t0[i] * probe->fs_hz;
+    }
+    const int ang_blk = std::max(1, std::min(A, RF_LDS_FLOATS / n_samples));
+    for (int a0 = 0; a0 < A; a0 += ang_blk) {
+        a.ang0 = a0;
+        a.n_ang = std::min(ang_blk, A - a0);
+        const size_t lds = sizeof(float) * (size_t)a.n_ang * n_samples;
+        if (pos_static) {
+            hipLaunchKernelGGL(rf_synth_kernel<true>, dim3(E, 1, 1), dim3(RF_THREADS), lds, s, a);
+        } else {
+            hipLaunchKernelGGL(rf_synth_kernel<false>, dim3(E, n_frames, 1), dim3(RF_THREADS), lds, s, a);
+        }
+        FQ_LAUNCH_CHECK();
+    }
+    return FQ_OK;
+}
