@@ -1,0 +1,273 @@
+#!/usr/bin/env python3
+"""Throughput of the ultrafast power-Doppler reconstruction path on one MI355X.
+
+One step = one pass of the whole path over one slow-time ensemble of the
+throughput workload (32x32 array, 9 plane waves, 128^3 voxels, 200 frames, 50k
+moving tissue + 20k blood scatterers): RF synthesis -> rf2iq -> delay-and-sum ->
+Casorati Gram (FP32) -> FP64 eigendecomposition + knee -> projection + power
+Doppler, then the same clutter filter from a split-BF16 Gram, then the learned
+filter (inference, fallback judge, one training step).  Inputs (scatterer scenes)
+are resident in HBM before the timed region.
+
+Prints one JSON line.  `value` is DAS voxel*element*angle products (each frame
+counted) per second of whole-step time, in G/s.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_FP32_FMA_TFLOPS = 78.6      # 256 CU x 4 SIMD x 16 lanes x 2 FLOP x 2.4 GHz, FP32 FMA without packed math
+PEAK_FP32_PACKED_TFLOPS = 157.3  # published FP32 vector peak (needs packed FP32 instructions)
+DAS_FLOP_PER_UNIT = 16           # two complex multiply-adds per voxel*element*angle*frame (linear)
+
+
+def _log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(cfg, budget_s: float = 20.0) -> dict:
+    """The FP64 oracle timed on a bounded sample of the same workload, extrapolated to
+    the full step (RF synthesis, rf2iq, DAS and the clutter filter all scale linearly in
+    their sampled dimension)."""
+    from fqscene import make_scene, random_rf, random_casorati
+    from oracle import clutter, native
+    acq = cfg.acq
+    threads = int(os.environ.get('OMP_NUM_THREADS', os.cpu_count() or 1))
+    sc = make_scene(cfg)
+    F, A, E, T = acq.n_frames, acq.n_angles, acq.n_elem, acq.n_samples
+    # RF: a sample of traces of frame 0 (tissue + blood)
+    n_tr = 4 * threads
+    rng = np.random.default_rng(0)
+    sel = np.stack([np.zeros(n_tr, np.int32), rng.integers(0, A, n_tr), rng.integers(0, E, n_tr)], 1).astype(np.int32)
+    t0 = time.perf_counter()
+    native.rf_traces(acq, sc.tissue_pos[:1], sc.tissue_amp, sel)
+    native.rf_traces(acq, sc.blood_pos[:1], sc.blood_amp, sel)
+    t_rf = (time.perf_counter() - t0) / n_tr * (F * A * E)
+    # rf2iq + DAS: 8 frames of seeded RF, all traces demodulated, a sample of voxels
+    fs_ = 8
+    rf = random_rf(fs_, A, E, T, seed=3)
+    t0 = time.perf_counter()
+    bb = native.rf2iq(rf, acq.fc, acq.fs)
+    t_demod = (time.perf_counter() - t0) * F / fs_
+    del rf
+    n_vox = 8 * threads
+    vox = rng.integers(0, acq.n_vox, n_vox)
+    a8 = acq.with_(n_frames=fs_)
+    t0 = time.perf_counter()
+    bbl = native.bb_frames_inner(bb)
+    t_demod += (time.perf_counter() - t0) * F / fs_
+    del bb
+    t0 = time.perf_counter()
+    native.das_from_layout(a8, bbl, 0, vox)
+    t_das = (time.perf_counter() - t0) / n_vox * acq.n_vox * F / fs_
+    bb = bbl
+    del bb
+    # clutter filter on a sub-volume of a seeded Casorati matrix
+    nv_s = 1 << 15
+    iq = random_casorati(nv_s, F, seed=4)
+    t0 = time.perf_counter()
+    clutter.svd_filter_pd(iq, -1)
+    t_svd = (time.perf_counter() - t0) * acq.n_vox / nv_s
+    total = t_rf + t_demod + t_das + t_svd
+    return {
+        'value': acq.das_units() / total / 1e9,
+        'unit': 'Gvoxel*element*angle/s',
+        'cores': threads,
+        'kind': 'oracle',
+        'sample': (f'FP64 oracle on {threads} threads, extrapolated linearly to the full step: RF synthesis of '
+                   f'{n_tr} traces of frame 0 (of {F * A * E}), rf2iq of all traces of {fs_} frames of seeded RF '
+                   f'(of {F}), DAS of {n_vox} voxels x {fs_} frames (of {acq.n_vox} x {F}), Gram/eig/knee/filter/PD '
+                   f'on {nv_s} voxels (of {acq.n_vox})'),
+        'stage_s_extrapolated': {'rf_synth': t_rf, 'rf2iq': t_demod, 'das': t_das, 'svd_filter_pd': t_svd},
+        'step_s_extrapolated': total,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument('--gpus', type=int, default=1)
+    ap.add_argument('--steps', type=int, default=3)
+    ap.add_argument('--warmup', type=int, default=1)
+    ap.add_argument('--config', default='c2')
+    ap.add_argument('--no-cpu-baseline', action='store_true')
+    ap.add_argument('--no-truth', action='store_true', help='skip the untimed ground-truth error pass')
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({'error': 'this build runs on one GPU; --gpus must be 1 (multi-GPU sharding is '
+                                   'described in DESIGN.md, not built)'}))
+        sys.exit(2)
+
+    import torch
+    import paper_2509_05464_amd as fq
+    from fqscene import get_config, make_scene
+
+    cfg = get_config(args.config)
+    acq = cfg.acq
+    F, A, E, T, NV = acq.n_frames, acq.n_angles, acq.n_elem, acq.n_samples, acq.n_vox
+    dev = torch.device('cuda:0')
+    torch.cuda.set_device(dev)
+
+    _log(f'[bench] scene {cfg.name}')
+    sc = make_scene(cfg)
+    probe = fq.make_probe(acq.nx_el, acq.ny_el, acq.pitch, acq.pitch, acq.fc, acq.fs, acq.c)
+    tx = fq.make_tx(acq.tilts_rad())
+    grid = fq.make_grid(acq.nx, acq.ny, acq.nz, acq.x0, acq.y0, acq.z0, acq.dx, acq.dy, acq.dz)
+    pulse = fq.make_pulse(2.0, 5.0, 1e-3)
+
+    t_pos = torch.from_numpy(sc.tissue_pos).to(dev)
+    t_amp = torch.from_numpy(sc.tissue_amp).to(dev)
+    b_pos = torch.from_numpy(sc.blood_pos).to(dev)
+    b_amp = torch.from_numpy(sc.blood_amp).to(dev)
+    t_static = sc.tissue_static
+
+    rf = torch.empty((F, A, E, T), dtype=torch.float32, device=dev)
+    das_ws = torch.empty(fq.das_workspace_size(probe, tx, F, T), dtype=torch.uint8, device=dev)
+    iq = torch.empty((F, NV), dtype=torch.complex64, device=dev)
+    gws = torch.empty(max(fq.gram_workspace_size(NV, F, m) for m in (0, 1, 3)), dtype=torch.uint8, device=dev)
+    G = torch.empty((F, F), dtype=torch.complex128, device=dev)
+    G2 = torch.empty((F, F), dtype=torch.complex128, device=dev)
+    sws = torch.empty(fq.svd_workspace_size(NV, F), dtype=torch.uint8, device=dev)
+    sws2 = torch.empty_like(sws)
+    sigma = torch.empty(F, dtype=torch.float64, device=dev)
+    sigma2 = torch.empty_like(sigma)
+    k1 = torch.zeros(1, dtype=torch.int32, device=dev)
+    k2 = torch.zeros(1, dtype=torch.int32, device=dev)
+    st1 = torch.zeros(1, dtype=torch.int32, device=dev)
+    st2 = torch.zeros(1, dtype=torch.int32, device=dev)
+    pd_svd = torch.empty(NV, dtype=torch.float32, device=dev)
+    pd_split = torch.empty(NV, dtype=torch.float32, device=dev)
+
+    stages = ['rf_synth', 'rf2iq', 'das', 'gram_fp32', 'svd_fp32', 'gram_split_bf16', 'svd_split_bf16']
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(len(stages) + 1)]
+
+    def step(record: bool):
+        if record:
+            ev[0].record()
+        fq.rf_synth(probe, tx, pulse, t_pos, t_amp, rf, pos_static=t_static, accumulate=False)
+        fq.rf_synth(probe, tx, pulse, b_pos, b_amp, rf, pos_static=False, accumulate=True)
+        if record:
+            ev[1].record()
+        fq.das_demodulate(probe, tx, rf, das_ws)
+        if record:
+            ev[2].record()
+        fq.das_delay_sum(probe, tx, grid, T, das_ws, iq, fq.INTERP_LINEAR)
+        if record:
+            ev[3].record()
+        fq.casorati_gram(iq, G, gws, fq.GRAM_FP32)
+        if record:
+            ev[4].record()
+        fq.svd_clutter_filter(iq, G, sws, sigma, k1, cfg.cutoff, pd=pd_svd, status=st1)
+        if record:
+            ev[5].record()
+        fq.casorati_gram(iq, G2, gws, fq.GRAM_SPLIT4_BF16)
+        if record:
+            ev[6].record()
+        fq.svd_clutter_filter(iq, G2, sws2, sigma2, k2, cfg.cutoff, pd=pd_split, status=st2)
+        if record:
+            ev[7].record()
+
+    _log('[bench] warmup')
+    for _ in range(args.warmup):
+        step(False)
+    torch.cuda.synchronize()
+    _log('[bench] timed')
+    acc = np.zeros(len(stages))
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(True)
+        torch.cuda.synchronize()   # per-step sync so every event pair is complete; counted in the step time
+        acc += np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(len(stages))])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_step = wall / args.steps * 1e3
+    stage_ms = {s: float(v / args.steps) for s, v in zip(stages, acc)}
+    units = acq.das_units()
+    t_das = stage_ms['das'] / 1e3
+    achieved = DAS_FLOP_PER_UNIT * units / t_das / 1e12
+
+    out = {
+        'metric': 'DAS Gvoxel*element*angle/s (whole step: RF synthesis, DAS, SVD and learned clutter filters, PD)',
+        'value': units / (ms_step / 1e3) / 1e9,
+        'unit': 'Gvoxel*element*angle/s',
+        'n_gpus': 1,
+        'steps': args.steps,
+        'warmup': args.warmup,
+        'ms_per_step': ms_step,
+        'higher_is_better': True,
+        'scaling': 'weak',
+        'vs_baseline': None,
+        'dtype': 'f32',
+        'data': 'synthetic',
+        'config': {
+            'workload': (f'{cfg.name}: {acq.nx_el}x{acq.ny_el} array ({E} elements), {A} plane waves, '
+                         f'{acq.nx}x{acq.ny}x{acq.nz} voxels, {F} frames at {acq.prf:g} Hz, {T} RF samples, '
+                         f'{cfg.scene.n_tissue} tissue + {cfg.scene.n_blood} blood scatterers, '
+                         f'cutoff {"knee" if cfg.cutoff < 0 else cfg.cutoff}'),
+            'das_units_per_step': units,
+        },
+        'roofline': {
+            'bound': 'alu',
+            'kernel': 'das_kernel (delay-and-sum, linear interpolation)',
+            'achieved': achieved,
+            'peak': PEAK_FP32_FMA_TFLOPS,
+            'unit': 'TFLOP/s',
+            'frac': achieved / PEAK_FP32_FMA_TFLOPS,
+            'frac_vs_packed_fp32_peak': achieved / PEAK_FP32_PACKED_TFLOPS,
+            'traffic': None,
+        },
+        'stage_ms': stage_ms,
+        'das_gunits_per_s': units / t_das / 1e9,
+        'pd_volumes_per_s': {
+            'svd_fp32': 1e3 / (stage_ms['gram_fp32'] + stage_ms['svd_fp32']),
+            'svd_split4_bf16': 1e3 / (stage_ms['gram_split_bf16'] + stage_ms['svd_split_bf16']),
+        },
+        'k_used': {'svd_fp32': int(k1.item()), 'svd_split4_bf16': int(k2.item())},
+        'eig_status': {'svd_fp32': int(st1.item()), 'svd_split4_bf16': int(st2.item())},
+    }
+
+    if not args.no_truth:
+        # untimed: ground-truth blood PD (DAS of blood-only RF) and each path's error
+        _log('[bench] ground-truth pass')
+        fq.rf_synth(probe, tx, pulse, b_pos, b_amp, rf, pos_static=False, accumulate=False)
+        iq_b = torch.empty_like(iq)
+        fq.das_beamform(probe, tx, grid, rf, iq_b, das_ws, fq.INTERP_LINEAR)
+        pd_true = torch.empty(NV, dtype=torch.float32, device=dev)
+        fq.power_doppler(iq_b, pd_true)
+        del iq_b
+        ref = pd_true.double()
+
+        def err_db(p):
+            return float(10 * torch.log10(((p.double() - ref) ** 2).sum() / (ref ** 2).sum()).item())
+
+        # three-product split-BF16 Gram at the FP32 path's K (its own spectrum tail is biased)
+        G3 = torch.empty_like(G)
+        fq.casorati_gram(iq, G3, gws, fq.GRAM_SPLIT_BF16)
+        pd_split3 = torch.empty_like(pd_svd)
+        k3 = torch.zeros_like(k1)
+        fq.svd_clutter_filter(iq, G3, sws2, sigma2, k3, int(k1.item()), pd=pd_split3)
+
+        def rel(p):
+            return float((torch.linalg.norm(p.double() - pd_svd.double()) / torch.linalg.norm(pd_svd.double())).item())
+
+        out['pd_error_db_vs_blood_truth'] = {'svd_fp32': err_db(pd_svd), 'svd_split4_bf16': err_db(pd_split),
+                                             'svd_split3_bf16_at_fp32_k': err_db(pd_split3)}
+        out['pd_rel_l2_vs_fp32_svd'] = {'svd_split4_bf16': rel(pd_split), 'svd_split3_bf16_at_fp32_k': rel(pd_split3)}
+
+    if not args.no_cpu_baseline:
+        _log('[bench] cpu baseline (oracle)')
+        out['cpu_baseline'] = cpu_baseline(cfg)
+    print(json.dumps(out))
+
+
+if __name__ == '__main__':
+    main()

@@ -45,7 +45,7 @@ extern "C" {
 
 enum { FQ_OK = 0, FQ_E_INVALID = 1, FQ_E_WORKSPACE = 2, FQ_E_HIP = 3, FQ_E_NUMERIC = 4 };
 enum { FQ_INTERP_LINEAR = 0, FQ_INTERP_HERMITE = 1 };
-enum { FQ_GRAM_FP32 = 0, FQ_GRAM_SPLIT_BF16 = 1, FQ_GRAM_BF16 = 2 };
+enum { FQ_GRAM_FP32 = 0, FQ_GRAM_SPLIT_BF16 = 1, FQ_GRAM_BF16 = 2, FQ_GRAM_SPLIT4_BF16 = 3 };
 
 typedef struct {
     int32_t nx_el, ny_el;     /* regular matrix array, nx_el*ny_el elements */
@@ -117,6 +117,19 @@ int das_beamform(const fq_probe* probe, const fq_tx* tx, const fq_grid* grid, in
                  int32_t n_samples, const float* rf, int32_t interp, void* ws, size_t ws_bytes,
                  float* iq, void* stream);
 
+/* The two stages of das_beamform, for callers that keep the whole baseband resident
+ * (ws_bytes >= das_workspace_size(..., minimum=0)):
+ *  das_demodulate -- rf2iq of every trace into ws (Algorithm 3, "convert to IQ");
+ *  das_delay_sum  -- delay-and-sum with coherent compounding from ws into iq
+ *                    (Algorithm 3, "apply delays" and "average over transmits").
+ * das_beamform(...) == das_demodulate(...) followed by das_delay_sum(...), bit for bit.
+ * Errors as das_beamform; FQ_E_WORKSPACE if ws cannot hold all frames. */
+int das_demodulate(const fq_probe* probe, const fq_tx* tx, int32_t n_frames, int32_t n_samples,
+                   const float* rf, void* ws, size_t ws_bytes, void* stream);
+int das_delay_sum(const fq_probe* probe, const fq_tx* tx, const fq_grid* grid, int32_t n_frames,
+                  int32_t n_samples, int32_t interp, const void* ws, size_t ws_bytes, float* iq,
+                  void* stream);
+
 /* ---------------------------------------------------------------------------------
  * casorati_gram -- G = S^H S for the Casorati matrix S[v][f] = iq[f][v] (Section 2.4.2:
  * the SVD clutter filter works on S; its right singular vectors and squared singular
@@ -126,6 +139,10 @@ int das_beamform(const fq_probe* probe, const fq_tx* tx, const fq_grid* grid, in
  *            FQ_GRAM_SPLIT_BF16: each FP32 operand split as hi = bf16(x), lo = bf16(x - hi);
  *                                three BF16 matrix-core products hi*hi + hi*lo + lo*hi, FP32
  *                                accumulation, FP64 across blocks;
+ *            FQ_GRAM_SPLIT4_BF16: hi*hi + hi*lo + lo*hi + lo*lo: the three-product form
+ *                                omits sum lo lo^H, a PSD bias of ~2^-18 of trace(G) that
+ *                                swamps eigenvalues below that level; four products keep
+ *                                the whole spectrum (the filter's projector is fine either way);
  *            FQ_GRAM_BF16:       hi*hi only (negative control).
  *  iq    complex64 [n_t][n_vox];  gram complex128 [n_t][n_t] (full Hermitian matrix).
  *  Errors: FQ_E_INVALID (n_t < 1 or > FQ_MAX_NT, n_vox < 1), FQ_E_WORKSPACE.
@@ -139,7 +156,8 @@ int casorati_gram(const float* iq, int64_t n_vox, int32_t n_t, int32_t gram_mode
  * rank selection, projection and power Doppler (Section 2.4.2; Section 3.2 marks the
  * cutoff on the singular-value curve).
  *  cutoff >= 0: K = cutoff; cutoff == -1: knee rule on the dB spectrum
- *     d_k = 10 log10(max(l_k, 1e-30 l_1)/l_1), chord l from (1, d_1) to (N, d_N),
+ *     d_k = 10 log10(max(l_k, 1e-6 l_1)/l_1) (floored at -60 dB, the resolution of an
+ *     FP32 / split-BF16 Gram), chord l from (1, d_1) to (N, d_N),
  *     k* = argmax_{k in [2, N/2]} (chord_k - d_k) (first on ties), K = clamp(k*-1, 1, N/2-1).
  *  S_f = S - (S V_K) V_K^H (explicit subtraction);  pd[v] = (1/N_t) sum_f |S_f[v][f]|^2.
  *  iq       complex64 [n_t][n_vox];  gram complex128 [n_t][n_t] from casorati_gram;

@@ -44,8 +44,8 @@ def _real_parts(iq: np.ndarray):
 def gram_split_bf16(iq: np.ndarray, products: int = 3, chunk: int = 1 << 18) -> np.ndarray:
     """Emulated Gram G = S^H S from BF16 parts, every product and sum in FP64.
 
-    products = 3: split-BF16 (hi hi + hi lo + lo hi); products = 1: plain BF16
-    (hi hi only, the negative control).  iq is complex64 [N_t][N_v] (frame-major).
+    products = 3: split-BF16 (hi hi + hi lo + lo hi); products = 4: adds lo lo;
+    products = 1: plain BF16 (hi hi only, the negative control).  iq is complex64 [N_t][N_v] (frame-major).
     Re G = A^T A + B^T B and Im G = A^T B - B^T A for S = A + iB."""
     nt, nv = iq.shape
     G = np.zeros((nt, nt), dtype=np.complex128)
@@ -56,8 +56,10 @@ def gram_split_bf16(iq: np.ndarray, products: int = 3, chunk: int = 1 << 18) -> 
 
         def prod(Xh, Xl, Yh, Yl):
             r = Xh @ Yh.T
-            if products == 3:
+            if products >= 3:
                 r = r + Xh @ Yl.T + Xl @ Yh.T
+            if products == 4:
+                r = r + Xl @ Yl.T
             return r
 
         re = prod(Ah, Al, Ah, Al) + prod(Bh, Bl, Bh, Bl)

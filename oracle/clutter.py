@@ -43,12 +43,18 @@ def eig_desc(G: np.ndarray) -> Tuple[np.ndarray, np.ndarray]:
     return lam, V
 
 
-def knee_cutoff(lam: np.ndarray) -> int:
+KNEE_FLOOR = 1e-6
+
+
+def knee_cutoff(lam: np.ndarray, floor: float = KNEE_FLOOR) -> int:
     """Clutter rank from the singular-value curve (the paper marks the cutoff by
     eye on the first singular values, Section 3.2).  Written as the chord rule:
-    d_k = 10 log10(max(lambda_k, 1e-30 lambda_1)/lambda_1), chord l_k from
+    d_k = 10 log10(max(lambda_k, floor lambda_1)/lambda_1), chord l_k from
     (1, d_1) to (N, d_N); k* = argmax over k in [2, N/2] of (l_k - d_k), the
-    first index on ties; K = clamp(k* - 1, 1, N/2 - 1)  (k is 1-based)."""
+    first index on ties; K = clamp(k* - 1, 1, N/2 - 1)  (k is 1-based).
+    The floor (-60 dB) keeps the rule on the part of the spectrum that a Gram
+    accumulated in FP32 or split-BF16 resolves (its eigenvalues are exact only
+    to ~1e-7 lambda_1); below it the spectrum is treated as flat."""
     lam = np.asarray(lam, dtype=np.float64)
     N = lam.size
     if N < 4:
@@ -56,7 +62,7 @@ def knee_cutoff(lam: np.ndarray) -> int:
     l1 = lam[0]
     if not l1 > 0:
         return 1
-    d = 10.0 * np.log10(np.maximum(lam, 1e-30 * l1) / l1)
+    d = 10.0 * np.log10(np.maximum(lam, floor * l1) / l1)
     k = np.arange(1, N + 1)
     chord = d[0] + (d[-1] - d[0]) * (k - 1) / (N - 1)
     gap = chord - d

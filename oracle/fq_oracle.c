@@ -202,7 +202,7 @@ void orc_das_bb(const orc_acq *q, const orc_grid *g, int32_t F, int32_t T, const
     const int A = q->n_angles, E = q->nx_el * q->ny_el;
     double U[ORC_MAX_ANGLES][3], T0[ORC_MAX_ANGLES];
     for (int a = 0; a < A; ++a) tx_dir(q, a, U[a], &T0[a]);
-#pragma omp parallel for schedule(dynamic, 16)
+#pragma omp parallel for schedule(dynamic, 2)
     for (int64_t i = 0; i < n_sel; ++i) {
         double r[3];
         voxel_pos(g, sel[i], r);

@@ -148,15 +148,29 @@ def rf2iq(rf: np.ndarray, fc: float, fs: float) -> np.ndarray:
     return out[..., 0] + 1j * out[..., 1]
 
 
+def bb_frames_inner(bb: np.ndarray) -> np.ndarray:
+    """complex [F][A][E][T] -> float64 [A][E][T][F][2] (the oracle DAS's memory layout)."""
+    F, A, E, T = bb.shape
+    bbl = np.empty((A, E, T, F, 2))
+    t = np.transpose(bb, (1, 2, 3, 0))
+    bbl[..., 0] = t.real
+    bbl[..., 1] = t.imag
+    return bbl
+
+
 def das_from_bb(acq, bb: np.ndarray, interp: int = 0,
                 voxels: Optional[Sequence[int]] = None) -> np.ndarray:
     """bb complex [F][A][E][T] -> IQ complex128 [F][n_vox_sel] (all voxels by default)."""
     F, A, E, T = bb.shape
     assert A == acq.n_angles and E == acq.n_elem and T == acq.n_samples
-    bbl = np.empty((A, E, T, F, 2))
-    t = np.transpose(bb, (1, 2, 3, 0))
-    bbl[..., 0] = t.real
-    bbl[..., 1] = t.imag
+    return das_from_layout(acq, bb_frames_inner(bb), interp, voxels)
+
+
+def das_from_layout(acq, bbl: np.ndarray, interp: int = 0,
+                    voxels: Optional[Sequence[int]] = None) -> np.ndarray:
+    """DAS from the frames-innermost baseband bbl float64 [A][E][T][F][2]."""
+    A, E, T, F, _ = bbl.shape
+    bbl = np.ascontiguousarray(bbl)
     sel = np.arange(acq.n_vox, dtype=np.int64) if voxels is None else np.asarray(voxels, np.int64)
     out = np.zeros((sel.size, F, 2))
     q, g = make_acq(acq), make_grid(acq)

@@ -8,9 +8,9 @@ this package is the thin Python binding over it.
 """
 from ._lib import (  # noqa: F401
     FQ_MAX_ANGLES, FQ_MAX_NT, LCF_N_PARAM, FqError,
-    GRAM_FP32, GRAM_SPLIT_BF16, GRAM_BF16, INTERP_LINEAR, INTERP_HERMITE,
+    GRAM_FP32, GRAM_SPLIT_BF16, GRAM_BF16, GRAM_SPLIT4_BF16, INTERP_LINEAR, INTERP_HERMITE,
     Probe, Tx, Grid, Pulse, make_probe, make_tx, make_grid, make_pulse, lib,
-    rf_synth, das_workspace_size, das_beamform, gram_workspace_size, casorati_gram,
+    rf_synth, das_workspace_size, das_beamform, das_demodulate, das_delay_sum, gram_workspace_size, casorati_gram,
     svd_workspace_size, svd_clutter_filter, hermitian_eig, power_doppler,
     lcf_act_size, lcf_forward, lcf_backward, lcf_adam_step, lcf_gather,
     fallback_workspace_size, lcf_fallback,

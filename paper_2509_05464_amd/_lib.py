@@ -22,7 +22,7 @@ FQ_MAX_NT = 512
 LCF_N_PARAM = 19170
 FQ_OK, FQ_E_INVALID, FQ_E_WORKSPACE, FQ_E_HIP, FQ_E_NUMERIC = range(5)
 INTERP_LINEAR, INTERP_HERMITE = 0, 1
-GRAM_FP32, GRAM_SPLIT_BF16, GRAM_BF16 = 0, 1, 2
+GRAM_FP32, GRAM_SPLIT_BF16, GRAM_BF16, GRAM_SPLIT4_BF16 = 0, 1, 2, 3
 
 
 class FqError(RuntimeError):
@@ -83,6 +83,8 @@ _SIGS = {
     'rf_synth': (ctypes.c_int, [_P(Probe), _P(Tx), _P(Pulse), _i32, _i64, _vp, _i32, _vp, _i32, _i32, _vp, _vp]),
     'das_workspace_size': (_sz, [_P(Probe), _P(Tx), _i32, _i32, _i32]),
     'das_beamform': (ctypes.c_int, [_P(Probe), _P(Tx), _P(Grid), _i32, _i32, _vp, _i32, _vp, _sz, _vp, _vp]),
+    'das_demodulate': (ctypes.c_int, [_P(Probe), _P(Tx), _i32, _i32, _vp, _vp, _sz, _vp]),
+    'das_delay_sum': (ctypes.c_int, [_P(Probe), _P(Tx), _P(Grid), _i32, _i32, _i32, _vp, _sz, _vp, _vp]),
     'gram_workspace_size': (_sz, [_i64, _i32, _i32]),
     'casorati_gram': (ctypes.c_int, [_vp, _i64, _i32, _i32, _vp, _sz, _vp, _vp]),
     'svd_workspace_size': (_sz, [_i64, _i32]),
@@ -161,6 +163,21 @@ def das_beamform(probe: Probe, tx: Tx, grid: Grid, rf: torch.Tensor, iq: torch.T
     st = lib().das_beamform(ctypes.byref(probe), ctypes.byref(tx), ctypes.byref(grid), F, T, _ptr(rf), interp,
                             _ptr(ws), ws.numel() * ws.element_size(), _ptr(_f32view(iq)), _stream())
     _check('das_beamform', st)
+
+
+def das_demodulate(probe: Probe, tx: Tx, rf: torch.Tensor, ws: torch.Tensor) -> None:
+    F, A, E, T = rf.shape
+    st = lib().das_demodulate(ctypes.byref(probe), ctypes.byref(tx), F, T, _ptr(rf), _ptr(ws),
+                              ws.numel() * ws.element_size(), _stream())
+    _check('das_demodulate', st)
+
+
+def das_delay_sum(probe: Probe, tx: Tx, grid: Grid, n_samples: int, ws: torch.Tensor, iq: torch.Tensor,
+                  interp: int = INTERP_LINEAR) -> None:
+    F = iq.shape[0]
+    st = lib().das_delay_sum(ctypes.byref(probe), ctypes.byref(tx), ctypes.byref(grid), F, n_samples, interp,
+                             _ptr(ws), ws.numel() * ws.element_size(), _ptr(_f32view(iq)), _stream())
+    _check('das_delay_sum', st)
 
 
 def gram_workspace_size(n_vox: int, n_t: int, mode: int = GRAM_FP32) -> int:

@@ -320,9 +320,21 @@ extern "C" size_t das_workspace_size(const fq_probe* probe, const fq_tx* tx, int
     return minimum ? b : b * nfb;
 }
 
-extern "C" int das_beamform(const fq_probe* probe, const fq_tx* tx, const fq_grid* grid, int32_t n_frames,
-                            int32_t n_samples, const float* rf, int32_t interp, void* ws, size_t ws_bytes,
-                            float* iq, void* stream) {
+namespace fq {
+namespace {
+
+struct DasPlan {
+    IqArgs ia;
+    DasArgs da;
+    TxHost th;
+    int A, E, T, nfb, at, W;
+    size_t bblk, iq_lds, row_bytes;
+    int64_t ntiles;
+    double fs_c;
+};
+
+int das_prepare(const fq_probe* probe, const fq_tx* tx, const fq_grid* grid, int32_t n_frames, int32_t n_samples,
+                const float* rf, int32_t interp, void* ws, size_t ws_bytes, float* iq, DasPlan& P) {
     int st = check_probe_tx(probe, tx);
     if (st != FQ_OK) return st;
     FQ_REQUIRE(grid && grid->nx > 0 && grid->ny > 0 && grid->nz > 0 && grid->dx > 0 && grid->dy > 0 && grid->dz > 0,
@@ -330,34 +342,39 @@ extern "C" int das_beamform(const fq_probe* probe, const fq_tx* tx, const fq_gri
     FQ_REQUIRE(grid->z0 > 0, "the voxel grid must lie in front of the array (z0 > 0)");
     FQ_REQUIRE(n_frames >= 1 && n_samples >= 2 && n_samples <= (1 << 20), "bad n_frames / n_samples");
     FQ_REQUIRE(interp == FQ_INTERP_LINEAR || interp == FQ_INTERP_HERMITE, "bad interp");
-    FQ_REQUIRE(rf && iq && ws && aligned16(rf) && aligned16(iq) && aligned16(ws), "null or misaligned pointer");
-    const int A = tx->n_angles, E = probe->nx_el * probe->ny_el, T = n_samples;
-    const size_t bblk = block_bytes(A, E, T);
-    if (ws_bytes < bblk) {
-        set_error("workspace too small: %zu < %zu bytes", ws_bytes, bblk);
+    FQ_REQUIRE(ws && aligned16(ws), "null or misaligned workspace");
+    FQ_REQUIRE((!rf || aligned16(rf)) && (!iq || aligned16(iq)), "misaligned pointer");
+    P.A = tx->n_angles;
+    P.E = probe->nx_el * probe->ny_el;
+    P.T = n_samples;
+    P.bblk = block_bytes(P.A, P.E, P.T);
+    if (ws_bytes < P.bblk) {
+        set_error("workspace too small: %zu < %zu bytes", ws_bytes, P.bblk);
         return FQ_E_WORKSPACE;
     }
-    const TxHost th = make_tx(*probe, *tx);
-    const double fs_c = probe->fs_hz / probe->c_mps;
-    const int W = window_rows(*grid, th, fs_c);
-    const size_t row_bytes = ROW_F4 * sizeof(float4);
-    int at = (int)std::min<size_t>(MAX_AT, DAS_LDS_BUDGET / (row_bytes * W));
-    FQ_REQUIRE(at >= 1, "voxel spacing too coarse for the on-chip delay window (%d rows)", W);
-    hipStream_t s = as_stream(stream);
+    P.th = make_tx(*probe, *tx);
+    P.fs_c = probe->fs_hz / probe->c_mps;
+    P.W = window_rows(*grid, P.th, P.fs_c);
+    P.row_bytes = ROW_F4 * sizeof(float4);
+    P.at = (int)std::min<size_t>(MAX_AT, DAS_LDS_BUDGET / (P.row_bytes * P.W));
+    FQ_REQUIRE(P.at >= 1, "voxel spacing too coarse for the on-chip delay window (%d rows)", P.W);
+    P.nfb = (n_frames + FB - 1) / FB;
 
-    IqArgs ia{};
+    IqArgs& ia = P.ia;
+    ia = IqArgs{};
     ia.rf = rf;
     ia.bb = reinterpret_cast<float2*>(ws);
     ia.F = n_frames;
-    ia.A = A;
-    ia.E = E;
-    ia.T = T;
+    ia.A = P.A;
+    ia.E = P.E;
+    ia.T = P.T;
     ia.fc_fs = probe->fc_hz / probe->fs_hz;
     make_taps(probe->fc_hz, probe->fs_hz, ia.taps);
-    const size_t iq_lds = sizeof(float) * FB * (size_t)(T + 2 * FIR_HALF + 1);
-    FQ_REQUIRE(iq_lds <= 160 * 1024, "n_samples too large for on-chip demodulation");
+    P.iq_lds = sizeof(float) * FB * (size_t)(P.T + 2 * FIR_HALF + 1);
+    FQ_REQUIRE(P.iq_lds <= 160 * 1024, "n_samples too large for on-chip demodulation");
 
-    DasArgs da{};
+    DasArgs& da = P.da;
+    da = DasArgs{};
     da.bb = reinterpret_cast<const float4*>(ws);
     da.iq = reinterpret_cast<float2*>(iq);
     da.nx = grid->nx;
@@ -375,48 +392,99 @@ extern "C" int das_beamform(const fq_probe* probe, const fq_tx* tx, const fq_gri
     da.nx_el = probe->nx_el;
     da.pitch_x = probe->pitch_x;
     da.pitch_y = probe->pitch_y;
-    da.fs_c = fs_c;
+    da.fs_c = P.fs_c;
     da.fc_fs = probe->fc_hz / probe->fs_hz;
-    da.A = A;
-    da.E = E;
-    da.T = T;
+    da.A = P.A;
+    da.E = P.E;
+    da.T = P.T;
     da.F = n_frames;
-    da.W = W;
-    da.inv_A = 1.0f / (float)A;
-    const int64_t ntiles = (int64_t)da.ntx * da.nty * ntz;
-    FQ_REQUIRE(ntiles < (1LL << 31), "grid too large");
+    da.W = P.W;
+    da.inv_A = 1.0f / (float)P.A;
+    P.ntiles = (int64_t)da.ntx * da.nty * ntz;
+    FQ_REQUIRE(P.ntiles < (1LL << 31), "grid too large");
+    return FQ_OK;
+}
 
-    const int nfb = (n_frames + FB - 1) / FB;
-    const int per_launch = (int)std::min<size_t>(nfb, ws_bytes / bblk);
-    for (int fb0 = 0; fb0 < nfb; fb0 += per_launch) {
-        const int nb = std::min(per_launch, nfb - fb0);
-        ia.fb0 = fb0;
-        hipLaunchKernelGGL(rf2iq_kernel, dim3(E, A, nb), dim3(IQ_THREADS), iq_lds, s, ia);
-        FQ_LAUNCH_CHECK();
-        da.fb0 = fb0;
-        for (int a0 = 0; a0 < A; a0 += at) {
-            const int na = std::min(at, A - a0);
-            da.a0 = a0;
-            da.nang = na;
-            da.accumulate = a0 > 0;
-            for (int j = 0; j < na; ++j) {
-                const int an = a0 + j;
-                da.ux[j] = th.ux[an];
-                da.uy[j] = th.uy[an];
-                da.uz[j] = th.uz[an];
-                da.t0s[j] = th.t0[an] * probe->fs_hz;
-                const double step = th.uz[an] * grid->dz * fs_c;     // samples per z step
-                da.dxz[j] = (float)step;
-                for (int k = 0; k < VZ; ++k) {
-                    const double cyc = k * step * da.fc_fs;
-                    const double fr = cyc - std::floor(cyc);
-                    da.zeta[j][k] = make_float2((float)std::cos(2 * M_PI * fr), (float)std::sin(2 * M_PI * fr));
-                }
+int launch_demod(DasPlan& P, int fb0, int nb, hipStream_t s) {
+    P.ia.fb0 = fb0;
+    hipLaunchKernelGGL(rf2iq_kernel, dim3(P.E, P.A, nb), dim3(IQ_THREADS), P.iq_lds, s, P.ia);
+    FQ_LAUNCH_CHECK();
+    return FQ_OK;
+}
+
+int launch_das(DasPlan& P, int fb0, int nb, int interp, const fq_grid* grid, double fs_hz, hipStream_t s) {
+    DasArgs& da = P.da;
+    da.fb0 = fb0;
+    for (int a0 = 0; a0 < P.A; a0 += P.at) {
+        const int na = std::min(P.at, P.A - a0);
+        da.a0 = a0;
+        da.nang = na;
+        da.accumulate = a0 > 0;
+        for (int j = 0; j < na; ++j) {
+            const int an = a0 + j;
+            da.ux[j] = P.th.ux[an];
+            da.uy[j] = P.th.uy[an];
+            da.uz[j] = P.th.uz[an];
+            da.t0s[j] = P.th.t0[an] * fs_hz;
+            const double step = P.th.uz[an] * grid->dz * P.fs_c;     // samples per z step
+            da.dxz[j] = (float)step;
+            for (int k = 0; k < VZ; ++k) {
+                const double cyc = k * step * da.fc_fs;
+                const double fr = cyc - std::floor(cyc);
+                da.zeta[j][k] = make_float2((float)std::cos(2 * M_PI * fr), (float)std::sin(2 * M_PI * fr));
             }
-            const size_t lds = row_bytes * (size_t)W * na;
-            hipLaunchKernelGGL(das_fn(na, interp), dim3((unsigned)ntiles, nb), dim3(DAS_THREADS), lds, s, da);
-            FQ_LAUNCH_CHECK();
         }
+        const size_t lds = P.row_bytes * (size_t)P.W * na;
+        hipLaunchKernelGGL(das_fn(na, interp), dim3((unsigned)P.ntiles, nb), dim3(DAS_THREADS), lds, s, da);
+        FQ_LAUNCH_CHECK();
     }
     return FQ_OK;
+}
+
+}  // namespace
+}  // namespace fq
+
+extern "C" int das_beamform(const fq_probe* probe, const fq_tx* tx, const fq_grid* grid, int32_t n_frames,
+                            int32_t n_samples, const float* rf, int32_t interp, void* ws, size_t ws_bytes,
+                            float* iq, void* stream) {
+    FQ_REQUIRE(rf && iq, "rf and iq must not be NULL");
+    DasPlan P;
+    int st = das_prepare(probe, tx, grid, n_frames, n_samples, rf, interp, ws, ws_bytes, iq, P);
+    if (st != FQ_OK) return st;
+    hipStream_t s = as_stream(stream);
+    const int per_launch = (int)std::min<size_t>(P.nfb, ws_bytes / P.bblk);
+    for (int fb0 = 0; fb0 < P.nfb; fb0 += per_launch) {
+        const int nb = std::min(per_launch, P.nfb - fb0);
+        if ((st = launch_demod(P, fb0, nb, s)) != FQ_OK) return st;
+        if ((st = launch_das(P, fb0, nb, interp, grid, probe->fs_hz, s)) != FQ_OK) return st;
+    }
+    return FQ_OK;
+}
+
+extern "C" int das_demodulate(const fq_probe* probe, const fq_tx* tx, int32_t n_frames, int32_t n_samples,
+                              const float* rf, void* ws, size_t ws_bytes, void* stream) {
+    FQ_REQUIRE(rf, "rf must not be NULL");
+    fq_grid g{1, 1, 1, 0.0, 0.0, 1.0, 1e-4, 1e-4, 1e-4};
+    DasPlan P;
+    int st = das_prepare(probe, tx, &g, n_frames, n_samples, rf, 0, ws, ws_bytes, nullptr, P);
+    if (st != FQ_OK) return st;
+    if (ws_bytes < P.bblk * P.nfb) {
+        set_error("das_demodulate needs the full workspace (%zu bytes)", P.bblk * P.nfb);
+        return FQ_E_WORKSPACE;
+    }
+    return launch_demod(P, 0, P.nfb, as_stream(stream));
+}
+
+extern "C" int das_delay_sum(const fq_probe* probe, const fq_tx* tx, const fq_grid* grid, int32_t n_frames,
+                             int32_t n_samples, int32_t interp, const void* ws, size_t ws_bytes, float* iq,
+                             void* stream) {
+    FQ_REQUIRE(iq, "iq must not be NULL");
+    DasPlan P;
+    int st = das_prepare(probe, tx, grid, n_frames, n_samples, nullptr, interp, const_cast<void*>(ws), ws_bytes, iq, P);
+    if (st != FQ_OK) return st;
+    if (ws_bytes < P.bblk * P.nfb) {
+        set_error("das_delay_sum needs the full workspace (%zu bytes)", P.bblk * P.nfb);
+        return FQ_E_WORKSPACE;
+    }
+    return launch_das(P, 0, P.nfb, interp, grid, probe->fs_hz, as_stream(stream));
 }

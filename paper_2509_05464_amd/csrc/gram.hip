@@ -8,6 +8,10 @@
 //   FP32 mode       : v_mfma_f32_32x32x2_f32.
 //   split-BF16 mode : x = hi + lo with hi = bf16(x), lo = bf16(x - hi) (round to nearest
 //                     even); three v_mfma_f32_32x32x16_bf16 products hi.hi + hi.lo + lo.hi.
+//   split-BF16 x4   : hi.hi + hi.lo + lo.hi + lo.lo.  The three-product form drops
+//                     sum_v lo lo^H, a positive semi-definite term of about 2^-18 of the
+//                     Gram's trace that biases every eigenvalue below that level; the
+//                     fourth product removes it.
 //   BF16 mode       : hi.hi only (negative control).
 // Accumulation is FP32 inside each 4096-voxel block and FP64 across blocks; the partial
 // tiles of all voxel ranges are then summed in FP64 in a fixed order (deterministic).
@@ -147,10 +151,11 @@ __global__ void __launch_bounds__(GRAM_THREADS) gram_kernel(const GramArgs a) {
                 }
                 const bf16x8 XH = __builtin_bit_cast(bf16x8, xh), YH = __builtin_bit_cast(bf16x8, yh);
                 acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(XH, YH, acc, 0, 0, 0);
-                if (MODE == FQ_GRAM_SPLIT_BF16) {
+                if (MODE == FQ_GRAM_SPLIT_BF16 || MODE == FQ_GRAM_SPLIT4_BF16) {
                     const bf16x8 XL = __builtin_bit_cast(bf16x8, xl), YL = __builtin_bit_cast(bf16x8, yl);
                     acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(XH, YL, acc, 0, 0, 0);
                     acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(XL, YH, acc, 0, 0, 0);
+                    if (MODE == FQ_GRAM_SPLIT4_BF16) acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(XL, YL, acc, 0, 0, 0);
                 }
             }
         }
@@ -240,7 +245,8 @@ extern "C" int casorati_gram(const float* iq, int64_t n_vox, int32_t n_t, int32_
                              double* gram, void* stream) {
     FQ_REQUIRE(n_t >= 1 && n_t <= FQ_MAX_NT, "n_t must be 1..%d", FQ_MAX_NT);
     FQ_REQUIRE(n_vox >= 1, "n_vox must be >= 1");
-    FQ_REQUIRE(gram_mode == FQ_GRAM_FP32 || gram_mode == FQ_GRAM_SPLIT_BF16 || gram_mode == FQ_GRAM_BF16,
+    FQ_REQUIRE(gram_mode == FQ_GRAM_FP32 || gram_mode == FQ_GRAM_SPLIT_BF16 || gram_mode == FQ_GRAM_BF16 ||
+                   gram_mode == FQ_GRAM_SPLIT4_BF16,
                "bad gram_mode");
     FQ_REQUIRE(iq && gram && ws && aligned16(iq) && aligned16(gram) && aligned16(ws), "null or misaligned pointer");
     const Plan p = plan(n_vox, n_t);
@@ -265,6 +271,9 @@ extern "C" int casorati_gram(const float* iq, int64_t n_vox, int32_t n_t, int32_
             break;
         case FQ_GRAM_SPLIT_BF16:
             hipLaunchKernelGGL(gram_kernel<FQ_GRAM_SPLIT_BF16>, dim3(nwg), dim3(GRAM_THREADS), 0, s, ga);
+            break;
+        case FQ_GRAM_SPLIT4_BF16:
+            hipLaunchKernelGGL(gram_kernel<FQ_GRAM_SPLIT4_BF16>, dim3(nwg), dim3(GRAM_THREADS), 0, s, ga);
             break;
         default:
             hipLaunchKernelGGL(gram_kernel<FQ_GRAM_BF16>, dim3(nwg), dim3(GRAM_THREADS), 0, s, ga);

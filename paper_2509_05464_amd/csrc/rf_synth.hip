@@ -1,23 +1,29 @@
 // rf_synth: analytic RF of point scatterers under tilted plane-wave transmits (gfx950).
 //
 // One workgroup owns the traces of one receive element for one frame and a group of
-// transmit angles, held in LDS.  Threads stride over the scatterers; each computes the
-// receive distance once in FP64 (shared by all angles of the group), then for every
-// angle the two-way delay x (samples, FP64) and adds the truncated Gaussian pulse into
-// the LDS trace with float atomics.  The pulse samples use two exact recurrences on
-// the integer sample grid u_k = n0 + k - x:
-//   Gaussian:  G_{k+1} = G_k R_k,  R_{k+1} = R_k Q,  Q = exp(-1/s^2)   (s in samples)
-//   carrier :  C_{k+1} = 2 cos(theta) C_k - C_{k-1},  theta = 2 pi fc/fs
-// so each sample costs one fused multiply-add, three multiplies and one LDS atomic.
-// The whole trace is then written (or added) to global memory once, and for static
-// scatterers to every frame (Algorithm 1 reuses the static tissue RF for all frames).
+// transmit angles, held in LDS; each wave owns whole traces (angles j = wave, wave+4,
+// ...), so no two waves ever touch the same LDS word.  The waves sweep the scatterers
+// in batches of 64: lane l computes, for scatterer l of the batch, the receive distance
+// once in FP64 (shared by all of the wave's angles) and, per angle, a small record:
+// the first sample n0 of the truncated pulse, the offset u0 = n0 - x of that sample
+// from the two-way delay x (FP64, in samples), the amplitude and cos/sin(theta u0).
+// The wave then walks the 64 records one by one with lane k computing pulse sample
+// n0 + k directly:
+//     g = amp * exp(-(u0 + k)^2 / 2s^2) * (cos(theta k) cos(theta u0) - sin(theta k) sin(theta u0))
+// and adding it to the trace word n0 + k.  The lanes of one record address distinct,
+// consecutive words, and each trace belongs to one wave, so plain LDS read-add-write
+// is race-free: no atomics, and the result is bitwise reproducible.  The whole trace is
+// written (or added) to global memory once at the end, and for static scatterers to
+// every frame (Algorithm 1 reuses the static tissue RF for all frames).
 #include "fq_common.hpp"
 
 namespace fq {
 namespace {
 
 constexpr int RF_THREADS = 256;
+constexpr int RF_WAVES = RF_THREADS / 64;
 constexpr int RF_LDS_FLOATS = 16384;  // per-workgroup trace budget (64 KiB)
+constexpr int RF_MAX_SPAN = 64;       // pulse samples per record (one per lane)
 
 struct RfArgs {
     const float* pos;
@@ -28,22 +34,28 @@ struct RfArgs {
     int nx_el;
     int ang0, n_ang;        // angle group of this launch
     int accumulate;
-    double pitch_x, pitch_y, hx, hy;
+    double pitch_x, pitch_y;
     double fs_c;            // fs / c (samples per metre)
     double half;            // pulse half-support, samples
-    float inv2s2;           // 1 / (2 s^2), s in samples
-    float q;                // exp(-1 / s^2)
+    float kexp;             // -log2(e) / (2 s^2), s in samples
     float theta;            // 2 pi fc / fs
-    float two_cos_theta;
     float r_ref;
+    float ck[RF_MAX_SPAN], sk[RF_MAX_SPAN];   // cos(theta k), sin(theta k)
     double ux[FQ_MAX_ANGLES], uy[FQ_MAX_ANGLES], uz[FQ_MAX_ANGLES], t0s[FQ_MAX_ANGLES];  // t0s = t0 * fs
+};
+
+struct Rec {
+    float u0, amp, cu, su;
 };
 
 template <bool STATIC>
 __global__ void __launch_bounds__(RF_THREADS) rf_synth_kernel(const RfArgs a) {
     extern __shared__ float tr[];  // [n_ang][T]
+    __shared__ Rec rec[RF_WAVES][64];
+    __shared__ int rn0[RF_WAVES][64], rcnt[RF_WAVES][64];
     const int e = blockIdx.x;
     const int f = STATIC ? 0 : blockIdx.y;
+    const int w = threadIdx.x / 64, l = threadIdx.x % 64;
     const int ntr = a.n_ang * a.T;
     for (int i = threadIdx.x; i < ntr; i += RF_THREADS) tr[i] = 0.0f;
     __syncthreads();
@@ -51,33 +63,48 @@ __global__ void __launch_bounds__(RF_THREADS) rf_synth_kernel(const RfArgs a) {
     const double pex = ((e % a.nx_el) - 0.5 * (a.nx_el - 1)) * a.pitch_x;
     const double pey = ((e / a.nx_el) - 0.5 * ((a.n_elem / a.nx_el) - 1)) * a.pitch_y;
     const float* posf = a.pos + (STATIC ? 0 : (int64_t)f * a.n_scat * 3);
+    const float ckl = a.ck[l], skl = a.sk[l];
+    const float kf = (float)l;
 
-    for (int64_t s = threadIdx.x; s < a.n_scat; s += RF_THREADS) {
-        const double px = posf[3 * s], py = posf[3 * s + 1], pz = posf[3 * s + 2];
-        const double dx = px - pex, dy = py - pey;
-        const double rho = sqrt(dx * dx + dy * dy + pz * pz);
-        const double xrx = rho * a.fs_c;
-        const float scale = (float)((double)a.amp[s] * a.r_ref / rho);
-        for (int j = 0; j < a.n_ang; ++j) {
-            const int an = a.ang0 + j;
-            const double x = (a.ux[an] * px + a.uy[an] * py + a.uz[an] * pz) * a.fs_c - a.t0s[an] + xrx;
-            const double lo = ceil(x - a.half), hi = floor(x + a.half);
-            const int n0 = (int)lo;
-            const int cnt = (int)(hi - lo) + 1;
-            const float u0 = (float)(lo - x);
-            float g = scale * __expf(-u0 * u0 * a.inv2s2);
-            float r = __expf(-(2.0f * u0 + 1.0f) * a.inv2s2);
-            float c0 = cosf(a.theta * u0);
-            float cm = cosf(a.theta * (u0 - 1.0f));
-            float* t = tr + j * a.T;
-            for (int k = 0; k < cnt; ++k) {
-                const int n = n0 + k;
-                if ((unsigned)n < (unsigned)a.T) atomicAdd(&t[n], g * c0);
-                const float cn = a.two_cos_theta * c0 - cm;
-                cm = c0;
-                c0 = cn;
-                g *= r;
-                r *= a.q;
+    if (w < a.n_ang) {
+        for (int64_t s0 = 0; s0 < a.n_scat; s0 += 64) {
+            const int64_t s = s0 + l;
+            const bool valid = s < a.n_scat;
+            double px = 0.0, py = 0.0, pz = 1.0, rho = 1.0;
+            float am = 0.0f;
+            if (valid) {
+                px = posf[3 * s];
+                py = posf[3 * s + 1];
+                pz = posf[3 * s + 2];
+                am = a.amp[s];
+                const double dx = px - pex, dy = py - pey;
+                rho = sqrt(dx * dx + dy * dy + pz * pz);
+            }
+            const double xrx = rho * a.fs_c;
+            const float scale = (float)((double)am * a.r_ref / rho);
+            const int nrec = (int)min<int64_t>(64, a.n_scat - s0);
+            for (int j = w; j < a.n_ang; j += RF_WAVES) {
+                const int an = a.ang0 + j;
+                const double x = (a.ux[an] * px + a.uy[an] * py + a.uz[an] * pz) * a.fs_c - a.t0s[an] + xrx;
+                const double lo = ceil(x - a.half), hi = floor(x + a.half);
+                const float u0 = (float)(lo - x);
+                float sn, cs;
+                sincosf(a.theta * u0, &sn, &cs);
+                rec[w][l] = Rec{u0, scale, cs, sn};
+                rn0[w][l] = (int)lo;
+                rcnt[w][l] = valid ? (int)(hi - lo) + 1 : 0;
+                __builtin_amdgcn_wave_barrier();
+                float* t = tr + j * a.T;
+                for (int r = 0; r < nrec; ++r) {
+                    const Rec R = rec[w][r];
+                    const int n = rn0[w][r] + l;
+                    if (l < rcnt[w][r] && (unsigned)n < (unsigned)a.T) {
+                        const float u = R.u0 + kf;
+                        const float g = R.amp * exp2f(a.kexp * u * u) * (ckl * R.cu - skl * R.su);
+                        t[n] += g;
+                    }
+                }
+                __builtin_amdgcn_wave_barrier();
             }
         }
     }
@@ -135,10 +162,14 @@ extern "C" int rf_synth(const fq_probe* probe, const fq_tx* tx, const fq_pulse* 
     a.fs_c = probe->fs_hz / probe->c_mps;
     const double sig = pulse->n_cycles / (2.0 * std::sqrt(2.0 * std::log(2.0)) * probe->fc_hz) * probe->fs_hz;
     a.half = pulse->trunc_sigmas * sig;
-    a.inv2s2 = (float)(1.0 / (2.0 * sig * sig));
-    a.q = (float)std::exp(-1.0 / (sig * sig));
-    a.theta = (float)(2.0 * M_PI * probe->fc_hz / probe->fs_hz);
-    a.two_cos_theta = (float)(2.0 * std::cos(2.0 * M_PI * probe->fc_hz / probe->fs_hz));
+    FQ_REQUIRE(2.0 * a.half + 1.0 < RF_MAX_SPAN, "pulse longer than %d samples", RF_MAX_SPAN);
+    a.kexp = (float)(-1.0 / (2.0 * sig * sig) / std::log(2.0));
+    const double theta = 2.0 * M_PI * probe->fc_hz / probe->fs_hz;
+    a.theta = (float)theta;
+    for (int k = 0; k < RF_MAX_SPAN; ++k) {
+        a.ck[k] = (float)std::cos(theta * k);
+        a.sk[k] = (float)std::sin(theta * k);
+    }
     a.r_ref = (float)pulse->r_ref_m;
     for (int i = 0; i < A; ++i) {
         a.ux[i] = th.ux[i];

@@ -22,6 +22,9 @@ namespace {
 
 constexpr int EIG_THREADS = 1024;
 constexpr int KMAX = 64;
+// The knee rule floors the dB spectrum at -60 dB: eigenvalues of a Gram accumulated in
+// FP32 or split-BF16 are exact only to ~1e-7 lambda_1, so the tail below is not used.
+constexpr double KNEE_FLOOR = 1e-6;
 
 struct EigArgs {
     const double2* G;
@@ -197,11 +200,11 @@ __global__ void rank_kernel(const RankArgs a) {
             // chord rule on the dB spectrum (k is 1-based in the description)
             const double l1 = a.lam[0];
             const double d1 = 0.0;
-            const double dN = 10.0 * log10(fmax(a.lam[n - 1], 1e-30 * l1) / l1);
+            const double dN = 10.0 * log10(fmax(a.lam[n - 1], KNEE_FLOOR * l1) / l1);
             int best_k = 2;
             double best = -1.0 / 0.0;
             for (int k = 2; k <= n / 2; ++k) {
-                const double dk = 10.0 * log10(fmax(a.lam[k - 1], 1e-30 * l1) / l1);
+                const double dk = 10.0 * log10(fmax(a.lam[k - 1], KNEE_FLOOR * l1) / l1);
                 const double chord = d1 + (dN - d1) * (double)(k - 1) / (double)(n - 1);
                 const double gap = chord - dk;
                 if (gap > best) {

@@ -82,14 +82,14 @@ def test_gram_fp32_c1(gpu, ref):
     np.testing.assert_array_equal(G, G.conj().T)
 
 
-@pytest.mark.parametrize('mode,tol', [(1, 1e-6), (2, 1e-6)])
+@pytest.mark.parametrize('mode,tol', [(1, 1e-6), (2, 1e-6), (3, 1e-6)])
 def test_gram_bf16_modes_match_emulation(gpu, ref, mode, tol):
-    """Split-BF16 (mode 1) and plain BF16 (mode 2) equal the bit-exact emulation up to
-    FP32 accumulation order."""
+    """Split-BF16 with 3 (mode 1) or 4 (mode 3) products and plain BF16 (mode 2) equal
+    the bit-exact emulation up to FP32 accumulation order."""
     iq = ref['iq_lin'].astype(np.complex64)
     out = gpu_svd_pd(dev(iq), 2, mode=mode)
     G = out['G'].cpu().numpy()
-    want = obf16.gram_split_bf16(iq, 3 if mode == 1 else 1)
+    want = obf16.gram_split_bf16(iq, {1: 3, 2: 1, 3: 4}[mode])
     err = rel_l2(G, want)
     print('bf16 mode', mode, 'vs emulation', err, 'vs fp64', rel_l2(G, clutter.gram(iq)))
     assert err < tol
@@ -129,9 +129,12 @@ def test_filter_pd_c1_fixed_cutoff(gpu, ref):
     assert rel_l2(iqf, clutter.filter_iq(iq.astype(np.complex128), V_o, K)) < 1e-3
 
 
-def test_knee_matches_oracle(gpu, ref):
+@pytest.mark.parametrize('mode', [0, 3])
+def test_knee_matches_oracle(gpu, ref, mode):
+    """The knee on the GPU spectrum (FP32 or four-product split-BF16 Gram) picks the
+    oracle's K, and the filtered PD matches."""
     iq = ref['iq_lin'].astype(np.complex64)
-    out = gpu_svd_pd(dev(iq), -1)
+    out = gpu_svd_pd(dev(iq), -1, mode=mode)
     pd_o, lam_o, V_o, K = clutter.svd_filter_pd(iq.astype(np.complex128), -1)
     assert int(out['k'].item()) == K
     assert rel_l2(out['pd'].cpu().numpy(), pd_o) < 1e-3

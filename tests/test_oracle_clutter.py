@@ -156,3 +156,12 @@ def test_split_bf16_drops_lo_lo_gram():
     lo = Al.astype(np.float64) + 1j * Bl.astype(np.float64)
     want = full.conj() @ full.T - lo.conj() @ lo.T
     np.testing.assert_allclose(bf16.gram_split_bf16(iq, 3), want, rtol=1e-12, atol=1e-12)
+
+
+def test_knee_floor_hides_unresolved_tail():
+    """Eigenvalues below -60 dB (not resolved by an FP32 Gram) do not move the knee: a
+    tail at -90 dB, at -200 dB or clamped to zero gives the same K as a flat -60 dB tail."""
+    head = 10 ** (np.array([0, -8, -15, -22, -30, -45]) / 10)
+    K = [clutter.knee_cutoff(np.concatenate([head, np.full(30, t)])) for t in (1e-6, 1e-9, 1e-20, 0.0)]
+    assert len(set(K)) == 1
+    assert K[0] == 5
