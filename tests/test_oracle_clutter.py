@@ -164,4 +164,4 @@ def test_knee_floor_hides_unresolved_tail():
     head = 10 ** (np.array([0, -8, -15, -22, -30, -45]) / 10)
     K = [clutter.knee_cutoff(np.concatenate([head, np.full(30, t)])) for t in (1e-6, 1e-9, 1e-20, 0.0)]
     assert len(set(K)) == 1
-    assert K[0] == 5
+    assert K[0] == 6          # the six components above the floor are clutter
