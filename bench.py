@@ -147,7 +147,28 @@ def main():
     pd_svd = torch.empty(NV, dtype=torch.float32, device=dev)
     pd_split = torch.empty(NV, dtype=torch.float32, device=dev)
 
-    stages = ['rf_synth', 'rf2iq', 'das', 'gram_fp32', 'svd_fp32', 'gram_split_bf16', 'svd_split_bf16']
+    # learned filter: trained weights when present, and a small training set (untimed)
+    from paper_2509_05464_amd.learned import LearnedFilter
+    from paper_2509_05464_amd.train_lcf import make_pairs
+    from fqscene import batch_indices, lcf_init_weights
+    wpath = os.path.join(ROOT, 'paper_2509_05464_amd', 'weights', 'lcf_c4.npz')
+    filt = LearnedFilter.load(wpath, dev) if os.path.exists(wpath) else LearnedFilter(lcf_init_weights(0), dev)
+    _log('[bench] learned-filter training pairs')
+    tr_cfg = get_config('c4_train')
+    tr_mix, tr_blood = make_pairs(tr_cfg, [1000, 1001], dev)
+    BATCH = 4096
+    xb = torch.empty((tr_cfg.acq.n_frames, BATCH), dtype=torch.complex64, device=dev)
+    yb = torch.empty_like(xb)
+    pd_lcf = torch.empty(NV, dtype=torch.float32, device=dev)
+    pd_out = torch.empty(NV, dtype=torch.float32, device=dev)
+    fb_ws = torch.empty(fq.fallback_workspace_size(NV), dtype=torch.uint8, device=dev)
+    fb_flag = torch.zeros(1, dtype=torch.int32, device=dev)
+    fb_d = torch.zeros(1, dtype=torch.float32, device=dev)
+    idx_host = [torch.from_numpy(batch_indices(2 * tr_cfg.acq.n_vox, BATCH, 77 + i)).to(dev) for i in range(8)]
+    step_no = [0]
+
+    stages = ['rf_synth', 'rf2iq', 'das', 'gram_fp32', 'svd_fp32', 'gram_split_bf16', 'svd_split_bf16',
+              'lcf_infer', 'fallback', 'lcf_train_step']
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(len(stages) + 1)]
 
     def step(record: bool):
@@ -175,6 +196,19 @@ def main():
         fq.svd_clutter_filter(iq, G2, sws2, sigma2, k2, cfg.cutoff, pd=pd_split, status=st2)
         if record:
             ev[7].record()
+        filt.infer(iq, pd_lcf)
+        if record:
+            ev[8].record()
+        fq.lcf_fallback(pd_lcf, pd_svd, pd_out, fb_flag, fb_d, fb_ws, -10.0)
+        if record:
+            ev[9].record()
+        idx = idx_host[step_no[0] % len(idx_host)]
+        step_no[0] += 1
+        fq.lcf_gather(tr_mix, idx, xb)
+        fq.lcf_gather(tr_blood, idx, yb)
+        filt.train_step(xb, yb)
+        if record:
+            ev[10].record()
 
     _log('[bench] warmup')
     for _ in range(args.warmup):
@@ -230,7 +264,10 @@ def main():
         'pd_volumes_per_s': {
             'svd_fp32': 1e3 / (stage_ms['gram_fp32'] + stage_ms['svd_fp32']),
             'svd_split4_bf16': 1e3 / (stage_ms['gram_split_bf16'] + stage_ms['svd_split_bf16']),
+            'learned': 1e3 / stage_ms['lcf_infer'],
         },
+        'learned_fallback': {'flag': int(fb_flag.item()), 'discrepancy_db_vs_svd': float(fb_d.item()),
+                             'weights': os.path.basename(wpath) if os.path.exists(wpath) else 'untrained (seed 0)'},
         'k_used': {'svd_fp32': int(k1.item()), 'svd_split4_bf16': int(k2.item())},
         'eig_status': {'svd_fp32': int(st1.item()), 'svd_split4_bf16': int(st2.item())},
     }
@@ -260,7 +297,8 @@ def main():
             return float((torch.linalg.norm(p.double() - pd_svd.double()) / torch.linalg.norm(pd_svd.double())).item())
 
         out['pd_error_db_vs_blood_truth'] = {'svd_fp32': err_db(pd_svd), 'svd_split4_bf16': err_db(pd_split),
-                                             'svd_split3_bf16_at_fp32_k': err_db(pd_split3)}
+                                             'svd_split3_bf16_at_fp32_k': err_db(pd_split3),
+                                             'learned': err_db(pd_lcf), 'learned_with_fallback': err_db(pd_out)}
         out['pd_rel_l2_vs_fp32_svd'] = {'svd_split4_bf16': rel(pd_split), 'svd_split3_bf16_at_fp32_k': rel(pd_split3)}
 
     if not args.no_cpu_baseline:

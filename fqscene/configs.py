@@ -158,6 +158,12 @@ CONFIGS = {
                  cutoff=-1),
 }
 CONFIGS['c3'] = dataclasses.replace(CONFIGS['c2'], name='c3')
+# small learned-filter case for tests: the small array and transmits, a 32^3 grid, 64
+# frames, moving tissue and three random vessels (the throughput workload's scene recipe)
+CONFIGS['c4_small'] = Config('c4_small', _acq(16, 16, _T3X, 32, 32, 32, 64, 1000.0, 512),
+                             SceneSpec(n_tissue=3000, tissue_std=1.0, n_blood=1500, blood_std=0.01,
+                                       vessels='random3', motion='cardiac_resp', seed=2000),
+                             cutoff=-1)
 
 
 def get_config(name: str) -> Config:

@@ -134,8 +134,8 @@ int das_delay_sum(const fq_probe* probe, const fq_tx* tx, const fq_grid* grid, i
  * casorati_gram -- G = S^H S for the Casorati matrix S[v][f] = iq[f][v] (Section 2.4.2:
  * the SVD clutter filter works on S; its right singular vectors and squared singular
  * values are the eigenpairs of G).
- *  gram_mode FQ_GRAM_FP32:       FP32 matrix-core products, FP32 accumulation within voxel
- *                                blocks, FP64 accumulation across blocks;
+ *  gram_mode FQ_GRAM_FP32:       FP32 matrix-core products, FP32 accumulation within
+ *                                64-voxel blocks, FP64 accumulation across blocks;
  *            FQ_GRAM_SPLIT_BF16: each FP32 operand split as hi = bf16(x), lo = bf16(x - hi);
  *                                three BF16 matrix-core products hi*hi + hi*lo + lo*hi, FP32
  *                                accumulation, FP64 across blocks;
@@ -209,9 +209,12 @@ int lcf_forward(const float* w, const uint16_t* w_bf16, const float* x, int64_t 
 
 /*  After lcf_forward(..., act, ...) on the same x: gradient of
  *  loss = mean over (series, channel, t) of (y - [Re, Im](target)/r)^2.
- *  grad float32 [19170] (overwritten); loss float32 [1] (device, overwritten). */
+ *  target complex64 [n_t][n_series]; act is consumed (the dz of each layer overwrites its
+ *  pre-activation, and its tail holds per-wave gradient partials, reduced in a fixed
+ *  order so the gradient is deterministic); grad float32 [19170] (overwritten);
+ *  loss float32 [1] (device, overwritten). */
 int lcf_backward(const float* w, const uint16_t* w_bf16, const float* x, const float* target,
-                 int64_t n_series, int32_t n_t, float eps, const uint16_t* act, float* grad,
+                 int64_t n_series, int32_t n_t, float eps, uint16_t* act, float* grad,
                  float* loss, void* stream);
 
 /*  Adam with bias correction on FP32 master weights; refreshes the BF16 copy.

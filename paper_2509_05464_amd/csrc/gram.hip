@@ -13,8 +13,11 @@
 //                     Gram's trace that biases every eigenvalue below that level; the
 //                     fourth product removes it.
 //   BF16 mode       : hi.hi only (negative control).
-// Accumulation is FP32 inside each 4096-voxel block and FP64 across blocks; the partial
-// tiles of all voxel ranges are then summed in FP64 in a fixed order (deterministic).
+// Accumulation is FP32 inside each 64-voxel stage and FP64 across stages (a long FP32
+// running sum of same-sign terms grows its rounding error with the sum; short blocks
+// keep the Gram exact to ~1e-8 of lambda_1, which the clutter subspace near the cutoff
+// needs); the partial tiles of all voxel ranges are then summed in FP64 in a fixed
+// order (deterministic).
 // Workgroups that share a voxel range are placed on the same XCD so the range is read
 // from HBM once and served to the other tiles from that XCD's L2.
 #include "fq_common.hpp"
@@ -29,7 +32,7 @@ typedef unsigned short ushortx8 __attribute__((ext_vector_type(8)));
 constexpr int GT = 32;            // tile edge, frames
 constexpr int KC = 64;            // voxels per LDS stage
 constexpr int LDW = KC + 4;       // LDS row stride (floats)
-constexpr int FLUSH = 4096 / KC;  // stages per FP32 accumulation block
+constexpr int FLUSH = 1;          // stages per FP32 accumulation block (64 voxels)
 constexpr int GRAM_THREADS = 256;
 constexpr int NXCD = 8;
 

@@ -1,10 +1,9 @@
 // rf_synth: analytic RF of point scatterers under tilted plane-wave transmits (gfx950).
 //
-// One workgroup owns the traces of one receive element for one frame and a group of
-// transmit angles, held in LDS; each wave owns whole traces (angles j = wave, wave+4,
-// ...), so no two waves ever touch the same LDS word.  The waves sweep the scatterers
-// in batches of 64: lane l computes, for scatterer l of the batch, the receive distance
-// once in FP64 (shared by all of the wave's angles) and, per angle, a small record:
+// One workgroup is one wavefront and owns one trace (frame, transmit, receive element),
+// held in LDS, so no two waves ever touch the same LDS word and small workgroups keep
+// many waves resident to hide LDS latency.  The wave sweeps the scatterers in batches of
+// 64: lane l computes, for scatterer l of the batch, in FP64 a small record:
 // the first sample n0 of the truncated pulse, the offset u0 = n0 - x of that sample
 // from the two-way delay x (FP64, in samples), the amplitude and cos/sin(theta u0).
 // The wave then walks the 64 records one by one with lane k computing pulse sample
@@ -20,9 +19,8 @@
 namespace fq {
 namespace {
 
-constexpr int RF_THREADS = 256;
-constexpr int RF_WAVES = RF_THREADS / 64;
-constexpr int RF_LDS_FLOATS = 16384;  // per-workgroup trace budget (64 KiB)
+constexpr int RF_THREADS = 64;       // one wave per workgroup, one trace per wave
+constexpr int RF_LDS_FLOATS = 16384;  // per-trace budget (64 KiB)
 constexpr int RF_MAX_SPAN = 64;       // pulse samples per record (one per lane)
 
 struct RfArgs {
@@ -32,7 +30,6 @@ struct RfArgs {
     int64_t n_scat;
     int n_frames, n_angles, n_elem, T;
     int nx_el;
-    int ang0, n_ang;        // angle group of this launch
     int accumulate;
     double pitch_x, pitch_y;
     double fs_c;            // fs / c (samples per metre)
@@ -50,74 +47,64 @@ struct Rec {
 
 template <bool STATIC>
 __global__ void __launch_bounds__(RF_THREADS) rf_synth_kernel(const RfArgs a) {
-    extern __shared__ float tr[];  // [n_ang][T]
-    __shared__ Rec rec[RF_WAVES][64];
-    __shared__ int rn0[RF_WAVES][64], rcnt[RF_WAVES][64];
+    extern __shared__ float tr[];  // [T]
+    __shared__ Rec rec[64];
+    __shared__ int rnc[64];        // n0 * 64 + count
     const int e = blockIdx.x;
     const int f = STATIC ? 0 : blockIdx.y;
-    const int w = threadIdx.x / 64, l = threadIdx.x % 64;
-    const int ntr = a.n_ang * a.T;
-    for (int i = threadIdx.x; i < ntr; i += RF_THREADS) tr[i] = 0.0f;
-    __syncthreads();
+    const int an = blockIdx.z;
+    const int l = threadIdx.x;
+    for (int i = l; i < a.T; i += RF_THREADS) tr[i] = 0.0f;
+    __builtin_amdgcn_wave_barrier();
 
     const double pex = ((e % a.nx_el) - 0.5 * (a.nx_el - 1)) * a.pitch_x;
     const double pey = ((e / a.nx_el) - 0.5 * ((a.n_elem / a.nx_el) - 1)) * a.pitch_y;
     const float* posf = a.pos + (STATIC ? 0 : (int64_t)f * a.n_scat * 3);
     const float ckl = a.ck[l], skl = a.sk[l];
     const float kf = (float)l;
+    const double ux = a.ux[an], uy = a.uy[an], uz = a.uz[an], t0s = a.t0s[an];
 
-    if (w < a.n_ang) {
-        for (int64_t s0 = 0; s0 < a.n_scat; s0 += 64) {
-            const int64_t s = s0 + l;
-            const bool valid = s < a.n_scat;
-            double px = 0.0, py = 0.0, pz = 1.0, rho = 1.0;
-            float am = 0.0f;
-            if (valid) {
-                px = posf[3 * s];
-                py = posf[3 * s + 1];
-                pz = posf[3 * s + 2];
-                am = a.amp[s];
-                const double dx = px - pex, dy = py - pey;
-                rho = sqrt(dx * dx + dy * dy + pz * pz);
-            }
-            const double xrx = rho * a.fs_c;
-            const float scale = (float)((double)am * a.r_ref / rho);
-            const int nrec = (int)min<int64_t>(64, a.n_scat - s0);
-            for (int j = w; j < a.n_ang; j += RF_WAVES) {
-                const int an = a.ang0 + j;
-                const double x = (a.ux[an] * px + a.uy[an] * py + a.uz[an] * pz) * a.fs_c - a.t0s[an] + xrx;
-                const double lo = ceil(x - a.half), hi = floor(x + a.half);
-                const float u0 = (float)(lo - x);
-                float sn, cs;
-                sincosf(a.theta * u0, &sn, &cs);
-                rec[w][l] = Rec{u0, scale, cs, sn};
-                rn0[w][l] = (int)lo;
-                rcnt[w][l] = valid ? (int)(hi - lo) + 1 : 0;
-                __builtin_amdgcn_wave_barrier();
-                float* t = tr + j * a.T;
-                for (int r = 0; r < nrec; ++r) {
-                    const Rec R = rec[w][r];
-                    const int n = rn0[w][r] + l;
-                    if (l < rcnt[w][r] && (unsigned)n < (unsigned)a.T) {
-                        const float u = R.u0 + kf;
-                        const float g = R.amp * exp2f(a.kexp * u * u) * (ckl * R.cu - skl * R.su);
-                        t[n] += g;
-                    }
-                }
-                __builtin_amdgcn_wave_barrier();
+    for (int64_t s0 = 0; s0 < a.n_scat; s0 += 64) {
+        const int64_t s = s0 + l;
+        const bool valid = s < a.n_scat;
+        double px = 0.0, py = 0.0, pz = 1.0;
+        float am = 0.0f;
+        if (valid) {
+            px = posf[3 * s];
+            py = posf[3 * s + 1];
+            pz = posf[3 * s + 2];
+            am = a.amp[s];
+        }
+        const double dx = px - pex, dy = py - pey;
+        const double rho = sqrt(dx * dx + dy * dy + pz * pz);
+        const double x = (ux * px + uy * py + uz * pz) * a.fs_c - t0s + rho * a.fs_c;
+        const double lo = ceil(x - a.half), hi = floor(x + a.half);
+        const float u0 = (float)(lo - x);
+        float sn, cs;
+        sincosf(a.theta * u0, &sn, &cs);
+        rec[l] = Rec{u0, (float)((double)am * a.r_ref / rho), cs, sn};
+        rnc[l] = (int)lo * 64 + (valid ? (int)(hi - lo) + 1 : 0);
+        __builtin_amdgcn_wave_barrier();
+        const int nrec = (int)min<int64_t>(64, a.n_scat - s0);
+        for (int r = 0; r < nrec; ++r) {
+            const Rec R = rec[r];
+            const int nc = rnc[r];
+            const int n = (nc >> 6) + l;     // arithmetic shift: n0 may be negative
+            if (l < (nc & 63) && (unsigned)n < (unsigned)a.T) {
+                const float u = R.u0 + kf;
+                const float g = R.amp * exp2f(a.kexp * u * u) * (ckl * R.cu - skl * R.su);
+                tr[n] += g;
             }
         }
+        __builtin_amdgcn_wave_barrier();
     }
-    __syncthreads();
+    __builtin_amdgcn_wave_barrier();
 
     const int nf = STATIC ? a.n_frames : 1;
     for (int ff = 0; ff < nf; ++ff) {
         const int fo = STATIC ? ff : f;
-        for (int i = threadIdx.x; i < ntr; i += RF_THREADS) {
-            const int j = i / a.T, n = i - j * a.T;
-            const int64_t o = (((int64_t)fo * a.n_angles + a.ang0 + j) * a.n_elem + e) * a.T + n;
-            a.rf[o] = a.accumulate ? a.rf[o] + tr[i] : tr[i];
-        }
+        float* dst = a.rf + (((int64_t)fo * a.n_angles + an) * a.n_elem + e) * a.T;
+        for (int i = l; i < a.T; i += RF_THREADS) dst[i] = a.accumulate ? dst[i] + tr[i] : tr[i];
     }
 }
 
@@ -177,17 +164,12 @@ extern "C" int rf_synth(const fq_probe* probe, const fq_tx* tx, const fq_pulse* 
         a.uz[i] = th.uz[i];
         a.t0s[i] = th.t0[i] * probe->fs_hz;
     }
-    const int ang_blk = std::max(1, std::min(A, RF_LDS_FLOATS / n_samples));
-    for (int a0 = 0; a0 < A; a0 += ang_blk) {
-        a.ang0 = a0;
-        a.n_ang = std::min(ang_blk, A - a0);
-        const size_t lds = sizeof(float) * (size_t)a.n_ang * n_samples;
-        if (pos_static) {
-            hipLaunchKernelGGL(rf_synth_kernel<true>, dim3(E, 1, 1), dim3(RF_THREADS), lds, s, a);
-        } else {
-            hipLaunchKernelGGL(rf_synth_kernel<false>, dim3(E, n_frames, 1), dim3(RF_THREADS), lds, s, a);
-        }
-        FQ_LAUNCH_CHECK();
+    const size_t lds = sizeof(float) * (size_t)n_samples;
+    if (pos_static) {
+        hipLaunchKernelGGL(rf_synth_kernel<true>, dim3(E, 1, A), dim3(RF_THREADS), lds, s, a);
+    } else {
+        hipLaunchKernelGGL(rf_synth_kernel<false>, dim3(E, n_frames, A), dim3(RF_THREADS), lds, s, a);
     }
+    FQ_LAUNCH_CHECK();
     return FQ_OK;
 }
