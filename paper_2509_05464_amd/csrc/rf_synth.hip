@@ -1,19 +1,12 @@
 // rf_synth: analytic RF of point scatterers under tilted plane-wave transmits (gfx950).
 //
-// One workgroup is one wavefront and owns one trace (frame, transmit, receive element),
-// held in LDS, so no two waves ever touch the same LDS word and small workgroups keep
-// many waves resident to hide LDS latency.  The wave sweeps the scatterers in batches of
-// 64: lane l computes, for scatterer l of the batch, in FP64 a small record:
-// the first sample n0 of the truncated pulse, the offset u0 = n0 - x of that sample
-// from the two-way delay x (FP64, in samples), the amplitude and cos/sin(theta u0).
-// The wave then walks the 64 records one by one with lane k computing pulse sample
-// n0 + k directly:
-//     g = amp * exp(-(u0 + k)^2 / 2s^2) * (cos(theta k) cos(theta u0) - sin(theta k) sin(theta u0))
-// and adding it to the trace word n0 + k.  The lanes of one record address distinct,
-// consecutive words, and each trace belongs to one wave, so plain LDS read-add-write
-// is race-free: no atomics, and the result is bitwise reproducible.  The whole trace is
-// written (or added) to global memory once at the end, and for static scatterers to
-// every frame (Algorithm 1 reuses the static tissue RF for all frames).
+// One workgroup is one wavefront and owns one trace (frame, transmit, receive element)
+// held in LDS, so no two waves ever touch the same LDS word and the small workgroups
+// keep many waves resident.  Each lane takes a scatterer, computes its two-way delay x
+// in FP64 (samples) and runs the truncated Gaussian pulse through recurrences on the
+// sample grid (see the kernel).  The whole trace is written (or added) to global memory
+// once at the end, and for static scatterers to every frame (Algorithm 1 reuses the
+// static tissue RF for all frames).
 #include "fq_common.hpp"
 
 namespace fq {
@@ -21,7 +14,7 @@ namespace {
 
 constexpr int RF_THREADS = 64;       // one wave per workgroup, one trace per wave
 constexpr int RF_LDS_FLOATS = 16384;  // per-trace budget (64 KiB)
-constexpr int RF_MAX_SPAN = 64;       // pulse samples per record (one per lane)
+constexpr int RF_MAX_SPAN = 64;       // longest pulse, samples
 
 struct RfArgs {
     const float* pos;
@@ -35,66 +28,86 @@ struct RfArgs {
     double fs_c;            // fs / c (samples per metre)
     double half;            // pulse half-support, samples
     float kexp;             // -log2(e) / (2 s^2), s in samples
+    float q;                // exp(-1 / s^2)
     float theta;            // 2 pi fc / fs
+    float two_cos_theta;
     float r_ref;
-    float ck[RF_MAX_SPAN], sk[RF_MAX_SPAN];   // cos(theta k), sin(theta k)
     double ux[FQ_MAX_ANGLES], uy[FQ_MAX_ANGLES], uz[FQ_MAX_ANGLES], t0s[FQ_MAX_ANGLES];  // t0s = t0 * fs
 };
 
-struct Rec {
-    float u0, amp, cu, su;
-};
-
+// Lanes = scatterers variant.  Each lane runs the pulse of its own record through
+// two exact recurrences on the sample grid u_k = u0 + k:
+//   Gaussian  G_{k+1} = G_k R_k, R_{k+1} = R_k Q, Q = exp(-1/s^2)
+//   carrier   C_{k+1} = 2 cos(theta) C_k - C_{k-1}
+// (one FMA and three multiplies per sample).  In one round only lanes whose first
+// samples n0 differ modulo 64 write (a 64-slot LDS claim table, last writer wins); at
+// step k those lanes touch n0 + k, distinct words in distinct banks, so the
+// read-add-write is race- and conflict-free.  Losing lanes keep their record for the
+// next round; winners load the next scatterers (wave prefix sum over the free lanes).
 template <bool STATIC>
-__global__ void __launch_bounds__(RF_THREADS) rf_synth_kernel(const RfArgs a) {
+__global__ void __launch_bounds__(RF_THREADS) rf_synth_claim_kernel(const RfArgs a) {
     extern __shared__ float tr[];  // [T]
-    __shared__ Rec rec[64];
-    __shared__ int rnc[64];        // n0 * 64 + count
+    __shared__ int claim[64];
     const int e = blockIdx.x;
     const int f = STATIC ? 0 : blockIdx.y;
     const int an = blockIdx.z;
     const int l = threadIdx.x;
     for (int i = l; i < a.T; i += RF_THREADS) tr[i] = 0.0f;
+    claim[l] = -1;
     __builtin_amdgcn_wave_barrier();
 
     const double pex = ((e % a.nx_el) - 0.5 * (a.nx_el - 1)) * a.pitch_x;
     const double pey = ((e / a.nx_el) - 0.5 * ((a.n_elem / a.nx_el) - 1)) * a.pitch_y;
     const float* posf = a.pos + (STATIC ? 0 : (int64_t)f * a.n_scat * 3);
-    const float ckl = a.ck[l], skl = a.sk[l];
-    const float kf = (float)l;
     const double ux = a.ux[an], uy = a.uy[an], uz = a.uz[an], t0s = a.t0s[an];
+    const uint64_t below = (l == 0) ? 0ull : (~0ull >> (64 - l));
 
-    for (int64_t s0 = 0; s0 < a.n_scat; s0 += 64) {
-        const int64_t s = s0 + l;
-        const bool valid = s < a.n_scat;
-        double px = 0.0, py = 0.0, pz = 1.0;
-        float am = 0.0f;
-        if (valid) {
-            px = posf[3 * s];
-            py = posf[3 * s + 1];
-            pz = posf[3 * s + 2];
-            am = a.amp[s];
-        }
-        const double dx = px - pex, dy = py - pey;
-        const double rho = sqrt(dx * dx + dy * dy + pz * pz);
-        const double x = (ux * px + uy * py + uz * pz) * a.fs_c - t0s + rho * a.fs_c;
-        const double lo = ceil(x - a.half), hi = floor(x + a.half);
-        const float u0 = (float)(lo - x);
-        float sn, cs;
-        sincosf(a.theta * u0, &sn, &cs);
-        rec[l] = Rec{u0, (float)((double)am * a.r_ref / rho), cs, sn};
-        rnc[l] = (int)lo * 64 + (valid ? (int)(hi - lo) + 1 : 0);
-        __builtin_amdgcn_wave_barrier();
-        const int nrec = (int)min<int64_t>(64, a.n_scat - s0);
-        for (int r = 0; r < nrec; ++r) {
-            const Rec R = rec[r];
-            const int nc = rnc[r];
-            const int n = (nc >> 6) + l;     // arithmetic shift: n0 may be negative
-            if (l < (nc & 63) && (unsigned)n < (unsigned)a.T) {
-                const float u = R.u0 + kf;
-                const float g = R.amp * exp2f(a.kexp * u * u) * (ckl * R.cu - skl * R.su);
-                tr[n] += g;
+    bool has = false;
+    int n0 = 0, cnt = 0;
+    float g = 0.f, r = 0.f, c0 = 0.f, cm = 0.f;
+    int64_t next = 0;
+    for (int epoch = 1;; ++epoch) {
+        // refill the free lanes with the next scatterers
+        const uint64_t need = __ballot(!has);
+        if (!has) {
+            const int64_t s = next + __popcll(need & below);
+            if (s < a.n_scat) {
+                const double px = posf[3 * s], py = posf[3 * s + 1], pz = posf[3 * s + 2];
+                const double dx = px - pex, dy = py - pey;
+                const double rho = sqrt(dx * dx + dy * dy + pz * pz);
+                const double x = (ux * px + uy * py + uz * pz) * a.fs_c - t0s + rho * a.fs_c;
+                const double lo = ceil(x - a.half), hi = floor(x + a.half);
+                const float u0 = (float)(lo - x);
+                const float scale = (float)((double)a.amp[s] * a.r_ref / rho);
+                n0 = (int)lo;
+                cnt = (int)(hi - lo) + 1;
+                g = scale * exp2f(a.kexp * u0 * u0);
+                r = exp2f(a.kexp * (2.0f * u0 + 1.0f));
+                c0 = cosf(a.theta * u0);
+                cm = cosf(a.theta * (u0 - 1.0f));
+                has = true;
             }
+        }
+        next += __popcll(need);
+        if (!__ballot(has)) break;
+        // claim: one winner per residue of n0 modulo 64
+        const int slot = n0 & 63;
+        const int tag = (epoch << 6) | l;
+        if (has) claim[slot] = tag;
+        __builtin_amdgcn_wave_barrier();
+        const bool win = has && claim[slot] == tag;
+        __builtin_amdgcn_wave_barrier();
+        if (win) {
+            for (int k = 0; k < cnt; ++k) {
+                const int n = n0 + k;
+                if ((unsigned)n < (unsigned)a.T) tr[n] += g * c0;
+                const float cn = a.two_cos_theta * c0 - cm;
+                cm = c0;
+                c0 = cn;
+                g *= r;
+                r *= a.q;
+            }
+            has = false;
         }
         __builtin_amdgcn_wave_barrier();
     }
@@ -153,10 +166,8 @@ extern "C" int rf_synth(const fq_probe* probe, const fq_tx* tx, const fq_pulse* 
     a.kexp = (float)(-1.0 / (2.0 * sig * sig) / std::log(2.0));
     const double theta = 2.0 * M_PI * probe->fc_hz / probe->fs_hz;
     a.theta = (float)theta;
-    for (int k = 0; k < RF_MAX_SPAN; ++k) {
-        a.ck[k] = (float)std::cos(theta * k);
-        a.sk[k] = (float)std::sin(theta * k);
-    }
+    a.two_cos_theta = (float)(2.0 * std::cos(theta));
+    a.q = (float)std::exp(-1.0 / (sig * sig));
     a.r_ref = (float)pulse->r_ref_m;
     for (int i = 0; i < A; ++i) {
         a.ux[i] = th.ux[i];
@@ -166,9 +177,9 @@ extern "C" int rf_synth(const fq_probe* probe, const fq_tx* tx, const fq_pulse* 
     }
     const size_t lds = sizeof(float) * (size_t)n_samples;
     if (pos_static) {
-        hipLaunchKernelGGL(rf_synth_kernel<true>, dim3(E, 1, A), dim3(RF_THREADS), lds, s, a);
+        hipLaunchKernelGGL(rf_synth_claim_kernel<true>, dim3(E, 1, A), dim3(RF_THREADS), lds, s, a);
     } else {
-        hipLaunchKernelGGL(rf_synth_kernel<false>, dim3(E, n_frames, A), dim3(RF_THREADS), lds, s, a);
+        hipLaunchKernelGGL(rf_synth_claim_kernel<false>, dim3(E, n_frames, A), dim3(RF_THREADS), lds, s, a);
     }
     FQ_LAUNCH_CHECK();
     return FQ_OK;

@@ -1,0 +1,104 @@
+"""Edge cases through the C ABI: ragged voxel tiles and frame blocks, empty scenes,
+odd and tiny ensemble lengths, full cutoff, invalid arguments on the device path."""
+import numpy as np
+import pytest
+
+from fqscene import get_config, random_casorati
+from fqscene.scene import point_scene
+from helpers import dev, gpu_das, gpu_svd_pd, rel_l2, structs
+from oracle import clutter, native
+
+pytestmark = pytest.mark.gpu
+
+C1 = get_config('c1').acq
+
+
+@pytest.mark.parametrize('interp', [0, 1])
+def test_das_ragged_grid_and_frames(gpu, interp):
+    """19x23x13 voxels (no dimension a multiple of the 16x16x4 tile) and 11 frames
+    (a partial 8-frame block), against the oracle on seeded random RF."""
+    acq = C1.with_(nx=19, ny=23, nz=13, n_frames=11, z0=6e-3)
+    rng = np.random.default_rng(21)
+    rf = rng.standard_normal((acq.n_frames, acq.n_angles, acq.n_elem, acq.n_samples)).astype(np.float32)
+    iq = gpu_das(acq, dev(rf), interp).cpu().numpy()
+    want = native.das_from_bb(acq, native.rf2iq(rf, acq.fc, acq.fs), interp)
+    assert rel_l2(iq, want) < 1e-4
+
+
+def test_rf_synth_empty_scene(gpu):
+    import torch
+    acq = C1.with_(n_frames=3)
+    probe, tx, grid, pulse = structs(acq)
+    rf = torch.full((3, acq.n_angles, acq.n_elem, acq.n_samples), 7.0, dtype=torch.float32, device='cuda')
+    empty = torch.zeros((1, 0, 3), dtype=torch.float32, device='cuda')
+    gpu.rf_synth(probe, tx, pulse, empty, torch.zeros(0, dtype=torch.float32, device='cuda'), rf, accumulate=True)
+    assert float(rf.min()) == 7.0 and float(rf.max()) == 7.0
+    gpu.rf_synth(probe, tx, pulse, empty, torch.zeros(0, dtype=torch.float32, device='cuda'), rf, accumulate=False)
+    assert float(rf.abs().max()) == 0.0
+
+
+def test_rf_synth_scatterer_at_record_edges(gpu):
+    """Pulses cut by the start and the end of the record (taps outside [0, T) dropped)."""
+    acq = C1.with_(n_frames=1, tilts_deg=((0.0, 0.0),), n_samples=200)
+    probe, tx, grid, pulse = structs(acq)
+    z_early = 1.0 * 1540 / 31.25e6 * 5        # arrives ~10 samples after t = 0
+    z_late = 1540 / 31.25e6 * 198 / 2          # arrives near the last sample
+    pos = np.array([[[0.0, 0.0, z_early], [0.3e-3, 0.1e-3, z_late]]], np.float32)
+    amp = np.array([1.0, -0.5], np.float32)
+    import torch
+    rf = torch.empty((1, 1, acq.n_elem, acq.n_samples), dtype=torch.float32, device='cuda')
+    gpu.rf_synth(probe, tx, pulse, dev(pos), dev(amp), rf)
+    sel = np.array([[0, 0, e] for e in range(acq.n_elem)], np.int32)
+    want = native.rf_traces(acq, pos, amp, sel)
+    assert rel_l2(rf.cpu().numpy().reshape(acq.n_elem, -1), want) < 2e-5
+
+
+@pytest.mark.parametrize('nt', [1, 3, 7, 33, 64])
+def test_gram_eig_small_and_odd_ensembles(gpu, nt):
+    import torch
+    iq = random_casorati(3000, nt, seed=nt, rank=min(2, nt)).astype(np.complex64)
+    out = gpu_svd_pd(dev(iq), min(1, nt))
+    G = out['G'].cpu().numpy()
+    Go = clutter.gram(iq)
+    assert rel_l2(G, Go) < 1e-6
+    ws = torch.empty(gpu.svd_workspace_size(3000, nt), dtype=torch.uint8, device='cuda')
+    lam = torch.empty(nt, dtype=torch.float64, device='cuda')
+    vecs = torch.empty((nt, nt), dtype=torch.complex128, device='cuda')
+    st = torch.full((1,), -1, dtype=torch.int32, device='cuda')
+    gpu.hermitian_eig(dev(Go), ws, lam, vecs, st)
+    lo, Vo = clutter.eig_desc(Go)
+    assert int(st.item()) == 0
+    np.testing.assert_allclose(lam.cpu().numpy(), lo, rtol=1e-9, atol=1e-12 * lo[0])
+    V = vecs.cpu().numpy()
+    np.testing.assert_allclose(V.conj().T @ V, np.eye(nt), atol=1e-10)
+    np.testing.assert_allclose((V * lam.cpu().numpy()) @ V.conj().T, Go, atol=1e-9 * np.abs(Go).max())
+
+
+def test_full_cutoff_removes_everything(gpu):
+    iq = random_casorati(2000, 12, seed=5).astype(np.complex64)
+    out = gpu_svd_pd(dev(iq), 12)
+    raw = clutter.power_doppler(iq)
+    assert float(out['pd'].abs().max()) < 1e-5 * raw.max()
+
+
+def test_degenerate_repeated_frames(gpu):
+    """All frames identical: rank-one Casorati, eigenvalues 0 after the first, PD ~ 0 for K = 1."""
+    rng = np.random.default_rng(4)
+    vol = (rng.standard_normal(5000) + 1j * rng.standard_normal(5000)).astype(np.complex64)
+    iq = np.repeat(vol[None], 10, 0)
+    out = gpu_svd_pd(dev(iq), 1)
+    s = out['sigma'].cpu().numpy()
+    assert s[1] < 1e-3 * s[0]        # round-off of the FP32-accumulated Gram only
+    assert float(out['pd'].max()) < 1e-8 * np.mean(np.abs(vol) ** 2)
+
+
+def test_invalid_workspace_is_reported(gpu):
+    import torch
+    acq = C1.with_(n_frames=2)
+    probe, tx, grid, _ = structs(acq)
+    rf = torch.zeros((2, acq.n_angles, acq.n_elem, acq.n_samples), dtype=torch.float32, device='cuda')
+    iq = torch.empty((2, acq.n_vox), dtype=torch.complex64, device='cuda')
+    ws = torch.empty(1024, dtype=torch.uint8, device='cuda')
+    with pytest.raises(gpu.FqError) as e:
+        gpu.das_beamform(probe, tx, grid, rf, iq, ws)
+    assert e.value.status == 2
