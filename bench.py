@@ -35,6 +35,31 @@ def _log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def measured_traffic(name: str):
+    """HBM bytes per launch of a kernel from its committed counter summary (FETCH_SIZE and
+    WRITE_SIZE runs, each scaled by a copy kernel of known size), or None when the
+    summary is missing or the kernel sources changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, 'profiles', name)
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if ':' in line and not line.startswith(('#', '|', ' ', '-')):
+            k, v = line.split(':', 1)
+            kv[k.strip()] = v.strip()
+    try:
+        h = hashlib.sha256()
+        for src in kv['sources'].split():
+            with open(os.path.join(ROOT, src), 'rb') as fh:
+                h.update(fh.read())
+        if h.hexdigest() != kv['sources_sha256']:
+            return None
+        return float(kv['traffic_bytes_per_launch'])
+    except (KeyError, OSError, ValueError):
+        return None
+
+
 def cpu_baseline(cfg, budget_s: float = 20.0) -> dict:
     """The FP64 oracle timed on a bounded sample of the same workload, extrapolated to
     the full step (RF synthesis, rf2iq, DAS and the clutter filter all scale linearly in
@@ -93,6 +118,38 @@ def cpu_baseline(cfg, budget_s: float = 20.0) -> dict:
     }
 
 
+def das_only(cfg, args, fq, torch, dev):
+    acq = cfg.acq
+    F, A, E, T, NV = acq.n_frames, acq.n_angles, acq.n_elem, acq.n_samples, acq.n_vox
+    probe = fq.make_probe(acq.nx_el, acq.ny_el, acq.pitch, acq.pitch, acq.fc, acq.fs, acq.c)
+    tx = fq.make_tx(acq.tilts_rad())
+    grid = fq.make_grid(acq.nx, acq.ny, acq.nz, acq.x0, acq.y0, acq.z0, acq.dx, acq.dy, acq.dz)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(3)
+    rf = torch.randn((F, A, E, T), device=dev, generator=gen)
+    ws = torch.empty(fq.das_workspace_size(probe, tx, F, T), dtype=torch.uint8, device=dev)
+    iq = torch.empty((F, NV), dtype=torch.complex64, device=dev)
+    fq.das_demodulate(probe, tx, rf, ws)
+    del rf
+    src = torch.zeros(1 << 31, dtype=torch.uint8, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)                      # calibration copy: 2 GiB read + 2 GiB written
+    for _ in range(args.warmup):
+        fq.das_delay_sum(probe, tx, grid, T, ws, iq)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        fq.das_delay_sum(probe, tx, grid, T, ws, iq)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    units = acq.das_units()
+    print(json.dumps({'kernel': 'das_kernel', 'workload': cfg.name, 'ms_per_launch': ms,
+                      'gunits_per_s': units / (ms / 1e3) / 1e9,
+                      'tflops': DAS_FLOP_PER_UNIT * units / (ms / 1e3) / 1e12}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument('--gpus', type=int, default=1)
@@ -101,6 +158,9 @@ def main():
     ap.add_argument('--config', default='c2')
     ap.add_argument('--no-cpu-baseline', action='store_true')
     ap.add_argument('--no-truth', action='store_true', help='skip the untimed ground-truth error pass')
+    ap.add_argument('--only', choices=['das'], default=None,
+                    help='das: the delay-and-sum kernel alone on the workload geometry (seeded random RF), '
+                         'plus a 2 GiB device copy that calibrates byte counters; for profiler runs')
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({'error': 'this build runs on one GPU; --gpus must be 1 (multi-GPU sharding is '
@@ -116,6 +176,8 @@ def main():
     F, A, E, T, NV = acq.n_frames, acq.n_angles, acq.n_elem, acq.n_samples, acq.n_vox
     dev = torch.device('cuda:0')
     torch.cuda.set_device(dev)
+    if args.only == 'das':
+        return das_only(cfg, args, fq, torch, dev)
 
     _log(f'[bench] scene {cfg.name}')
     sc = make_scene(cfg)
@@ -257,7 +319,8 @@ def main():
             'unit': 'TFLOP/s',
             'frac': achieved / PEAK_FP32_FMA_TFLOPS,
             'frac_vs_packed_fp32_peak': achieved / PEAK_FP32_PACKED_TFLOPS,
-            'traffic': None,
+            'traffic': measured_traffic('das_kernel_c2_hbm_traffic.md') if cfg.name in ('c2', 'c3') else None,
+            'traffic_unit': 'bytes per launch (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, copy-calibrated)',
         },
         'stage_ms': stage_ms,
         'das_gunits_per_s': units / t_das / 1e9,

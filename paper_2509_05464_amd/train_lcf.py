@@ -116,6 +116,7 @@ def main():
     ap.add_argument('--lr', type=float, default=1e-3)
     ap.add_argument('--init-seed', type=int, default=0)
     ap.add_argument('--eval-seed', type=int, default=None)
+    ap.add_argument('--eval-config', default=None, help='workload of the held-out volume (default: --config)')
     ap.add_argument('--out', default='lcf_weights.npz')
     args = ap.parse_args()
     lo, hi = (int(v) for v in args.seeds.split('-'))
@@ -128,8 +129,11 @@ def main():
     train(filt, mix, blood, args.steps, args.batch)
     filt.save(args.out)
     if args.eval_seed is not None:
-        m, b = make_pairs(cfg, [args.eval_seed])
-        print('[eval]', evaluate(filt, m[0], b[0]), flush=True)
+        del mix, blood
+        torch.cuda.empty_cache()
+        ecfg = get_config(args.eval_config or args.config)
+        m, b = make_pairs(ecfg, [args.eval_seed])
+        print('[eval]', ecfg.name, args.eval_seed, evaluate(filt, m[0], b[0]), flush=True)
 
 
 if __name__ == '__main__':
