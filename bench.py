@@ -150,6 +150,37 @@ def das_only(cfg, args, fq, torch, dev):
                       'tflops': DAS_FLOP_PER_UNIT * units / (ms / 1e3) / 1e12}))
 
 
+def rf_only(cfg, args, fq, torch, dev):
+    """RF synthesis of the workload's scene (tissue, then blood added), for profiler runs."""
+    from fqscene import make_scene
+    acq = cfg.acq
+    sc = make_scene(cfg)
+    probe = fq.make_probe(acq.nx_el, acq.ny_el, acq.pitch, acq.pitch, acq.fc, acq.fs, acq.c)
+    tx = fq.make_tx(acq.tilts_rad())
+    pulse = fq.make_pulse(2.0, 5.0, 1e-3)
+    t_pos, t_amp = torch.from_numpy(sc.tissue_pos).to(dev), torch.from_numpy(sc.tissue_amp).to(dev)
+    b_pos, b_amp = torch.from_numpy(sc.blood_pos).to(dev), torch.from_numpy(sc.blood_amp).to(dev)
+    rf = torch.empty((acq.n_frames, acq.n_angles, acq.n_elem, acq.n_samples), dtype=torch.float32, device=dev)
+
+    def run():
+        fq.rf_synth(probe, tx, pulse, t_pos, t_amp, rf, pos_static=sc.tissue_static, accumulate=False)
+        fq.rf_synth(probe, tx, pulse, b_pos, b_amp, rf, pos_static=False, accumulate=True)
+
+    for _ in range(args.warmup):
+        run()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        run()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    n_rec = (sc.tissue_amp.size + sc.blood_amp.size) * acq.n_elem * acq.n_angles * acq.n_frames
+    print(json.dumps({'kernel': 'rf_synth_kernel', 'workload': cfg.name, 'ms_per_step': ms,
+                      'records_per_s': n_rec / (ms / 1e3)}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument('--gpus', type=int, default=1)
@@ -158,9 +189,10 @@ def main():
     ap.add_argument('--config', default='c2')
     ap.add_argument('--no-cpu-baseline', action='store_true')
     ap.add_argument('--no-truth', action='store_true', help='skip the untimed ground-truth error pass')
-    ap.add_argument('--only', choices=['das'], default=None,
+    ap.add_argument('--only', choices=['das', 'rf'], default=None,
                     help='das: the delay-and-sum kernel alone on the workload geometry (seeded random RF), '
-                         'plus a 2 GiB device copy that calibrates byte counters; for profiler runs')
+                         'plus a 2 GiB device copy that calibrates byte counters; rf: RF synthesis of the '
+                         'workload scene alone; for profiler runs')
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({'error': 'this build runs on one GPU; --gpus must be 1 (multi-GPU sharding is '
@@ -178,6 +210,8 @@ def main():
     torch.cuda.set_device(dev)
     if args.only == 'das':
         return das_only(cfg, args, fq, torch, dev)
+    if args.only == 'rf':
+        return rf_only(cfg, args, fq, torch, dev)
 
     _log(f'[bench] scene {cfg.name}')
     sc = make_scene(cfg)

@@ -86,8 +86,10 @@ typedef struct {
  *  accumulate 0: rf is overwritten; 1: the echoes are added to rf (RF_total = RF_phantom +
  *             RF_flow of Algorithm 1 by two calls);
  *  rf         float32 [n_frames][n_angles][n_elem][n_samples].
- *  Errors: FQ_E_INVALID for null pointers, non-positive sizes, n_samples > 8192,
- *  n_angles*n_samples beyond the on-chip trace budget (40960).  n_scat == 0 is valid.
+ *  Errors: FQ_E_INVALID for null pointers, non-positive sizes, n_samples > 8192, a pulse
+ *  whose half-support trunc_sigmas*s*fs reaches 32 samples.  n_scat == 0 is valid.
+ *  The order in which echoes are summed depends on scheduling, so results agree with a
+ *  serial sum to FP32 rounding, not bit for bit.
  * ------------------------------------------------------------------------------- */
 int rf_synth(const fq_probe* probe, const fq_tx* tx, const fq_pulse* pulse, int32_t n_frames,
              int64_t n_scat, const float* pos, int32_t pos_static, const float* amp,
@@ -152,9 +154,9 @@ int casorati_gram(const float* iq, int64_t n_vox, int32_t n_t, int32_t gram_mode
                   size_t ws_bytes, double* gram, void* stream);
 
 /* ---------------------------------------------------------------------------------
- * svd_clutter_filter -- eigendecomposition of G in FP64 on the GPU (cyclic Jacobi),
- * rank selection, projection and power Doppler (Section 2.4.2; Section 3.2 marks the
- * cutoff on the singular-value curve).
+ * svd_clutter_filter -- eigendecomposition of G in FP64 on the GPU (Householder
+ * tridiagonalisation, implicit QL, back-transformation), rank selection, projection and
+ * power Doppler (Section 2.4.2; Section 3.2 marks the cutoff on the singular-value curve).
  *  cutoff >= 0: K = cutoff; cutoff == -1: knee rule on the dB spectrum
  *     d_k = 10 log10(max(l_k, 1e-6 l_1)/l_1) (floored at -60 dB, the resolution of an
  *     FP32 / split-BF16 Gram), chord l from (1, d_1) to (N, d_N),
@@ -164,8 +166,8 @@ int casorati_gram(const float* iq, int64_t n_vox, int32_t n_t, int32_t gram_mode
  *  iq_filt  complex64 [n_t][n_vox] or NULL;  pd float32 [n_vox] or NULL;
  *  sigma    float64 [n_t] singular values, descending (device);
  *  k_used   int32 [1] (device): the K applied;
- *  status   int32 [1] (device) or NULL: 0 ok, FQ_E_NUMERIC if the eigensolver did not
- *           converge (results are then those of the last sweep).
+ *  status   int32 [1] (device) or NULL: 0 ok, FQ_E_NUMERIC if the QL iteration did not
+ *           converge within 60 iterations per eigenvalue (outputs are then undefined).
  *  K is limited to 64 (FQ_E_INVALID for a larger fixed cutoff; the knee result is
  *  clamped to 64 and the status word set to FQ_E_NUMERIC).
  * ------------------------------------------------------------------------------- */
@@ -175,7 +177,8 @@ int svd_clutter_filter(const float* iq, int64_t n_vox, int32_t n_t, const double
                        double* sigma, int32_t* k_used, int32_t* status, void* stream);
 
 /* eigendecomposition only: lam float64 [n_t] descending (clamped >= 0), vecs complex128
- * [n_t][n_t] with column k the eigenvector of lam[k].  Same workspace as above. */
+ * [n_t][n_t] with column k the eigenvector of lam[k], or NULL for eigenvalues only.
+ * Same workspace and status word as above. */
 int hermitian_eig(const double* gram, int32_t n_t, void* ws, size_t ws_bytes, double* lam,
                   double* vecs, int32_t* status, void* stream);
 

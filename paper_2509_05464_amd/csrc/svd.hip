@@ -1,15 +1,18 @@
 // svd_clutter_filter / hermitian_eig / power_doppler (gfx950).
 //
-// Eigendecomposition of the N_t x N_t Hermitian Gram in FP64 by parallel cyclic Jacobi
-// in one workgroup: each round rotates N/2 disjoint index pairs (round-robin ordering),
-// so the two-sided update J^H A J splits into independent 2x2 blocks and V <- V J into
-// independent row pairs.  The complex rotation of a pair (p, q) with a = A_pp, d = A_qq,
-// b = A_pq = |b| e^{i phi} is J = diag(1, e^{-i phi}) R(theta), which first makes the
-// off-diagonal real and then annihilates it with a real Jacobi rotation
-// (cot 2 theta = (d - a) / 2|b|, smaller root t = tan theta).  A pair is rotated while
-// |b| > tol sqrt(a d) (relative criterion, suited to the graded spectrum of clutter).
-// Eigenvalues are then ranked in descending order, clamped at zero (round-off of a PSD
-// matrix), and the rank is chosen (fixed, or the knee of the dB spectrum).
+// Eigendecomposition of the N_t x N_t Hermitian Gram G = S^H S in FP64, in four steps:
+//  1. tridiagonalisation (one workgroup): for k = 0 .. n-2 a Householder reflector
+//     H_k = I - tau_k v_k v_k^H (v_k[k+1] = 1) maps column k below the diagonal to
+//     beta_k e_1 with beta_k real, and the trailing block is updated two-sided,
+//     A22 <- H^H A22 H = A22 - (v w^H + w v^H),  w = tau A22 v - |tau|^2 (v^H A22 v) v / 2.
+//     G = Q T Q^H with Q = H_0 H_1 ... and T real symmetric tridiagonal (d, e = beta).
+//  2. implicit QL with Wilkinson shifts on T (one lane, on T scaled to unit size): the
+//     eigenvalues, plus the log of every plane rotation in the order applied;
+//  3. replay of the log on the identity, row by row (each lane owns a row of Z, held in
+//     LDS), which gives T = Z diag(lambda) Z^T; columns are ranked by descending eigenvalue;
+//  4. back-transformation of the wanted columns, V = Q Z, one wavefront per column.
+// Eigenvalues are clamped at zero (round-off of a PSD matrix), and the rank is chosen
+// (fixed, or the knee of the dB spectrum).
 //
 // The projection S_f = S - (S V_K) V_K^H and the power Doppler are fused: one thread
 // per voxel reads its slow-time series twice (coalesced across voxels), first to form
@@ -20,161 +23,356 @@
 namespace fq {
 namespace {
 
-constexpr int EIG_THREADS = 1024;
+constexpr int TRI_THREADS = 1024;
 constexpr int KMAX = 64;
+constexpr int QL_MAX_ITER = 60;       // QL iterations per eigenvalue
+constexpr int ROT_PER_N2 = 8;         // rotation log capacity, in units of n^2 (typical use ~1.2)
 // The knee rule floors the dB spectrum at -60 dB: eigenvalues of a Gram accumulated in
 // FP32 or split-BF16 are exact only to ~1e-7 lambda_1, so the tail below is not used.
 constexpr double KNEE_FLOOR = 1e-6;
 
-struct EigArgs {
-    const double2* G;
-    double2* A;        // [m][m] work copy
-    double2* V;        // [m][m]
-    double* lam;       // [n] descending
-    double* sigma;     // [n] or null
-    double2* vecs;     // [n][n] or null
-    int* status;       // or null
-    int n, m, max_sweeps;
-    double tol;
-};
-
 __device__ __forceinline__ double2 zmul(double2 a, double2 b) {
     return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
-__device__ __forceinline__ double2 zscale(double s, double2 a) { return make_double2(s * a.x, s * a.y); }
-__device__ __forceinline__ double2 zadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ double2 zconj(double2 a) { return make_double2(a.x, -a.y); }
+// a * conj(b)
+__device__ __forceinline__ double2 zmulc(double2 a, double2 b) {
+    return make_double2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+}
 
-// slot j of the round-robin schedule in round r (m even): slot 0 fixed, others rotate
-__device__ __forceinline__ int rr_slot(int j, int r, int m) { return j == 0 ? 0 : 1 + (j - 1 + r) % (m - 1); }
-
-__global__ void __launch_bounds__(EIG_THREADS) jacobi_kernel(const EigArgs a) {
-    __shared__ double rc[FQ_MAX_NT / 2 + 1], rs[FQ_MAX_NT / 2 + 1];
-    __shared__ double2 re_[FQ_MAX_NT / 2 + 1];
-    __shared__ int rp[FQ_MAX_NT / 2 + 1], rq[FQ_MAX_NT / 2 + 1];
-    __shared__ double red[EIG_THREADS / 64];
-    __shared__ int any_rot;
-    const int n = a.n, m = a.m, h = m / 2, tid = threadIdx.x;
-
-    double fro = 0.0;
-    for (int idx = tid; idx < m * m; idx += EIG_THREADS) {
-        const int i = idx / m, j = idx % m;
-        double2 g = (i < n && j < n) ? a.G[i * n + j] : make_double2(0.0, 0.0);
-        if (i == j) g.y = 0.0;
-        a.A[idx] = g;
-        a.V[idx] = make_double2(i == j ? 1.0 : 0.0, 0.0);
-        fro += g.x * g.x + g.y * g.y;
-    }
-    for (int o = 32; o > 0; o >>= 1) fro += __shfl_xor(fro, o);
-    if ((tid & 63) == 0) red[tid >> 6] = fro;
+// sum over the workgroup; every thread gets the total (red holds one slot per wave)
+template <int NT>
+__device__ __forceinline__ double block_sum(double v, double* red) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    const int w = threadIdx.x >> 6;
     __syncthreads();
-    double tot = 0.0;
-    for (int w = 0; w < EIG_THREADS / 64; ++w) tot += red[w];
-    const double abs_tol = 1e-300 + 1e-18 * sqrt(tot);
+    if ((threadIdx.x & 63) == 0) red[w] = v;
+    __syncthreads();
+    double t = 0.0;
+#pragma unroll
+    for (int i = 0; i < NT / 64; ++i) t += red[i];
+    return t;
+}
 
-    int sweep = 0;
-    bool converged = false;
-    for (; sweep < a.max_sweeps; ++sweep) {
-        if (tid == 0) any_rot = 0;
-        __syncthreads();
-        for (int r = 0; r < m - 1; ++r) {
-            if (tid < h) {
-                int p = rr_slot(tid, r, m), q = rr_slot(m - 1 - tid, r, m);
-                if (p > q) {
-                    const int t = p;
-                    p = q;
-                    q = t;
-                }
-                const double app = a.A[p * m + p].x, aqq = a.A[q * m + q].x;
-                const double2 b = a.A[p * m + q];
-                const double mag = sqrt(b.x * b.x + b.y * b.y);
-                double c = 1.0, s = 0.0;
-                double2 e = make_double2(1.0, 0.0);
-                if (mag > fmax(a.tol * sqrt(fabs(app * aqq)), abs_tol)) {
-                    const double tau = (aqq - app) / (2.0 * mag);
-                    const double t = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-                    c = 1.0 / sqrt(1.0 + t * t);
-                    s = t * c;
-                    e = make_double2(b.x / mag, -b.y / mag);   // e^{-i phi}
-                    any_rot = 1;
-                }
-                rc[tid] = c;
-                rs[tid] = s;
-                re_[tid] = e;
-                rp[tid] = p;
-                rq[tid] = q;
+// ------------------------------------------------------------------ 1. tridiagonalisation
+struct TriArgs {
+    const double2* G;   // [n][n]
+    double2* A;         // [n][n] work copy
+    double2* vh;        // [n][n]: v_k in row k, entries k+1 .. n-1
+    double2* tau;       // [n]
+    double* d;          // [n]
+    double* e;          // [n]
+    int n;
+};
+
+__global__ void __launch_bounds__(TRI_THREADS) tridiag_kernel(const TriArgs a) {
+    __shared__ double2 sv[FQ_MAX_NT], sy[FQ_MAX_NT];
+    __shared__ double red[TRI_THREADS / 64];
+    __shared__ double2 s_tau, s_scale;
+    __shared__ int s_skip;
+    const int n = a.n, tid = threadIdx.x;
+    // Hermitian part of the input (the Gram is Hermitian up to its own rounding)
+    for (int idx = tid; idx < n * n; idx += TRI_THREADS) {
+        const int i = idx / n, j = idx - i * n;
+        const double2 g = a.G[idx], gt = a.G[j * n + i];
+        a.A[idx] = i == j ? make_double2(g.x, 0.0) : make_double2(0.5 * (g.x + gt.x), 0.5 * (g.y - gt.y));
+    }
+    __syncthreads();
+    for (int k = 0; k < n - 1; ++k) {
+        const int m = n - k - 1;            // length of the reflected part (rows k+1 .. n-1)
+        double ps = 0.0;
+        for (int i = k + 2 + tid; i < n; i += TRI_THREADS) {
+            const double2 x = a.A[i * n + k];
+            ps += x.x * x.x + x.y * x.y;
+        }
+        const double sigma = block_sum<TRI_THREADS>(ps, red);
+        if (tid == 0) {
+            const double2 alpha = a.A[(k + 1) * n + k];
+            double2 tau = make_double2(0.0, 0.0), scale = make_double2(0.0, 0.0);
+            double beta = alpha.x;
+            int skip = 1;
+            if (sigma > 0.0 || alpha.y != 0.0) {
+                const double nrm = sqrt(alpha.x * alpha.x + alpha.y * alpha.y + sigma);
+                beta = alpha.x >= 0.0 ? -nrm : nrm;
+                tau = make_double2((beta - alpha.x) / beta, -alpha.y / beta);
+                const double2 den = make_double2(alpha.x - beta, alpha.y);   // 1 / (alpha - beta)
+                const double dd = den.x * den.x + den.y * den.y;
+                scale = make_double2(den.x / dd, -den.y / dd);
+                skip = 0;
             }
-            __syncthreads();
-            // A <- J^H A J, one 2x2 block per (row pair i, column pair j)
-            for (int idx = tid; idx < h * h; idx += EIG_THREADS) {
-                const int i = idx / h, j = idx % h;
-                const int pi = rp[i], qi = rq[i], pj = rp[j], qj = rq[j];
-                const double ci = rc[i], si = rs[i], cj = rc[j], sj = rs[j];
-                const double2 ei = re_[i], ej = re_[j];
-                const double2 a00 = a.A[pi * m + pj], a01 = a.A[pi * m + qj];
-                const double2 a10 = a.A[qi * m + pj], a11 = a.A[qi * m + qj];
-                // M = A_blk J_j,  J_j = [[c, s], [-s e, c e]]
-                const double2 mse = zscale(-sj, ej), mce = zscale(cj, ej);
-                const double2 m00 = zadd(zscale(cj, a00), zmul(a01, mse));
-                const double2 m01 = zadd(zscale(sj, a00), zmul(a01, mce));
-                const double2 m10 = zadd(zscale(cj, a10), zmul(a11, mse));
-                const double2 m11 = zadd(zscale(sj, a10), zmul(a11, mce));
-                // J_i^H = [[c, -s conj e], [s, c conj e]]
-                const double2 ce = zconj(ei);
-                const double2 nse = zscale(-si, ce), nce = zscale(ci, ce);
-                double2 n00 = zadd(zscale(ci, m00), zmul(nse, m10));
-                double2 n01 = zadd(zscale(ci, m01), zmul(nse, m11));
-                double2 n10 = zadd(zscale(si, m00), zmul(nce, m10));
-                double2 n11 = zadd(zscale(si, m01), zmul(nce, m11));
-                if (i == j) {
-                    n00.y = 0.0;
-                    n11.y = 0.0;
-                    if (si != 0.0) {
-                        n01 = make_double2(0.0, 0.0);
-                        n10 = make_double2(0.0, 0.0);
-                    }
-                }
-                a.A[pi * m + pj] = n00;
-                a.A[pi * m + qj] = n01;
-                a.A[qi * m + pj] = n10;
-                a.A[qi * m + qj] = n11;
-            }
-            // V <- V J
-            for (int idx = tid; idx < m * h; idx += EIG_THREADS) {
-                const int row = idx / h, j = idx % h;
-                const double c = rc[j], s = rs[j];
-                if (s == 0.0) continue;
-                const double2 e = re_[j];
-                const int p = rp[j], q = rq[j];
-                const double2 vp = a.V[row * m + p], vq = a.V[row * m + q];
-                a.V[row * m + p] = zadd(zscale(c, vp), zmul(zscale(-s, e), vq));
-                a.V[row * m + q] = zadd(zscale(s, vp), zmul(zscale(c, e), vq));
-            }
-            __syncthreads();
+            a.tau[k] = tau;
+            a.e[k] = beta;
+            a.d[k] = a.A[k * n + k].x;
+            s_tau = tau;
+            s_scale = scale;
+            s_skip = skip;
         }
         __syncthreads();
-        if (!any_rot) {
-            converged = true;
-            break;
+        const double2 tau = s_tau, scale = s_scale;
+        const int skip = s_skip;
+        for (int i = tid; i < m; i += TRI_THREADS) {
+            const double2 v = i == 0 ? make_double2(1.0, 0.0) : zmul(a.A[(k + 1 + i) * n + k], scale);
+            sv[i] = v;
+            a.vh[k * n + k + 1 + i] = v;
+        }
+        __syncthreads();
+        if (skip) continue;
+        // y = A22 v, four threads per row
+        for (int row = tid >> 2; row < m; row += TRI_THREADS / 4) {
+            const double2* Ar = a.A + (size_t)(k + 1 + row) * n + (k + 1);
+            double2 acc = make_double2(0.0, 0.0);
+            for (int j = tid & 3; j < m; j += 4) {
+                const double2 x = Ar[j], v = sv[j];
+                acc.x += x.x * v.x - x.y * v.y;
+                acc.y += x.x * v.y + x.y * v.x;
+            }
+            acc.x += __shfl_xor(acc.x, 1);
+            acc.y += __shfl_xor(acc.y, 1);
+            acc.x += __shfl_xor(acc.x, 2);
+            acc.y += __shfl_xor(acc.y, 2);
+            if ((tid & 3) == 0) sy[row] = acc;
+        }
+        __syncthreads();
+        // r = v^H y (real for Hermitian A22)
+        double pr = 0.0;
+        for (int i = tid; i < m; i += TRI_THREADS) pr += sv[i].x * sy[i].x + sv[i].y * sy[i].y;
+        const double r = block_sum<TRI_THREADS>(pr, red);
+        const double hw = 0.5 * (tau.x * tau.x + tau.y * tau.y) * r;
+        for (int i = tid; i < m; i += TRI_THREADS) {
+            const double2 ty = zmul(tau, sy[i]);
+            sy[i] = make_double2(ty.x - hw * sv[i].x, ty.y - hw * sv[i].y);
+        }
+        __syncthreads();
+        // A22 -= v w^H + w v^H
+        for (int idx = tid; idx < m * m; idx += TRI_THREADS) {
+            const int i = idx / m, j = idx - i * m;
+            const double2 p = zmulc(sv[i], sy[j]), q = zmulc(sy[i], sv[j]);
+            double2* x = a.A + (size_t)(k + 1 + i) * n + (k + 1 + j);
+            const double2 o = *x;
+            *x = make_double2(o.x - p.x - q.x, o.y - p.y - q.y);
         }
         __syncthreads();
     }
+    if (tid == 0) {
+        a.d[n - 1] = a.A[(n - 1) * n + (n - 1)].x;
+        a.e[n - 1] = 0.0;
+    }
+}
 
-    // rank eigenvalues (descending, ties by index) and write outputs
-    for (int i = tid; i < n; i += EIG_THREADS) {
-        const double li = a.A[i * m + i].x;
-        int rank = 0;
-        for (int j = 0; j < n; ++j) {
-            const double lj = a.A[j * m + j].x;
-            rank += (lj > li) || (lj == li && j < i);
+// ------------------------------------------------------------------ 2. QL on T
+struct QlArgs {
+    const double* d;
+    const double* e;
+    int* rot_i;         // rotation log: plane (i, i+1), cos, sin
+    double* rot_c;
+    double* rot_s;
+    int* rot_n;
+    int cap;
+    double* lam;        // [n] descending, clamped at 0
+    double* sigma;      // [n] or null
+    int* perm;          // [n]: column of Z holding the eigenvalue of rank j
+    int* status;        // or null
+    int n;
+};
+
+__global__ void __launch_bounds__(64) ql_kernel(const QlArgs a) {
+    __shared__ double d[FQ_MAX_NT], e[FQ_MAX_NT];
+    __shared__ int s_bad;
+    const int n = a.n, l0 = threadIdx.x;
+    for (int i = l0; i < n; i += 64) {
+        d[i] = a.d[i];
+        e[i] = a.e[i];
+    }
+    __syncthreads();
+    if (l0 == 0) {
+        // scale T to unit size (no overflow in squares, scale-free tolerances)
+        double sc = 0.0;
+        for (int i = 0; i < n; ++i) sc = fmax(sc, fabs(d[i]) + fabs(e[i]));
+        const double isc = sc > 0.0 ? 1.0 / sc : 0.0;
+        for (int i = 0; i < n; ++i) {
+            d[i] *= isc;
+            e[i] *= isc;
         }
+        e[n - 1] = 0.0;
+        const double eps = 2.220446049250313e-16;
+        int cnt = 0, bad = 0;
+        for (int l = 0; l < n && !bad; ++l) {
+            for (int it = 0;; ++it) {
+                int m = l;
+                for (; m < n - 1; ++m) {
+                    const double dd = fabs(d[m]) + fabs(d[m + 1]);
+                    if (fabs(e[m]) <= eps * dd) break;
+                }
+                if (m == l) break;
+                if (it >= QL_MAX_ITER || cnt + (m - l) > a.cap) {
+                    bad = 1;
+                    break;
+                }
+                // Wilkinson shift from the leading 2x2 block
+                double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
+                double r = sqrt(g * g + 1.0);
+                g = d[m] - d[l] + e[l] / (g + (g >= 0.0 ? r : -r));
+                double s = 1.0, c = 1.0, p = 0.0;
+                int i = m - 1;
+                bool split = false;
+                for (; i >= l; --i) {
+                    const double f = s * e[i], b = c * e[i];
+                    r = sqrt(f * f + g * g);
+                    e[i + 1] = r;
+                    if (r == 0.0) {   // e[i] vanished: the block splits, restart
+                        d[i + 1] -= p;
+                        e[m] = 0.0;
+                        split = true;
+                        break;
+                    }
+                    s = f / r;
+                    c = g / r;
+                    g = d[i + 1] - p;
+                    r = (d[i] - g) * s + 2.0 * c * b;
+                    p = s * r;
+                    d[i + 1] = g + p;
+                    g = c * r - b;
+                    a.rot_i[cnt] = i;
+                    a.rot_c[cnt] = c;
+                    a.rot_s[cnt] = s;
+                    ++cnt;
+                }
+                if (split) continue;
+                d[l] -= p;
+                e[l] = g;
+                e[m] = 0.0;
+            }
+        }
+        for (int i = 0; i < n; ++i) d[i] *= sc;
+        *a.rot_n = cnt;
+        s_bad = bad;
+        if (a.status) *a.status = bad ? FQ_E_NUMERIC : FQ_OK;
+    }
+    __syncthreads();
+    // rank: descending, ties by index
+    for (int i = l0; i < n; i += 64) {
+        const double li = d[i];
+        int rank = 0;
+        for (int j = 0; j < n; ++j) rank += (d[j] > li) || (d[j] == li && j < i);
         const double lc = li > 0.0 ? li : 0.0;
         a.lam[rank] = lc;
         if (a.sigma) a.sigma[rank] = sqrt(lc);
-        if (a.vecs)
-            for (int row = 0; row < n; ++row) a.vecs[row * n + rank] = a.V[row * m + i];
+        a.perm[rank] = i;
     }
-    if (tid == 0 && a.status) *a.status = converged ? 0 : FQ_E_NUMERIC;
+}
+
+// ------------------------------------------------------------------ 3. replay of the log
+struct ReplayArgs {
+    const int* rot_i;
+    const double* rot_c;
+    const double* rot_s;
+    const int* rot_n;
+    const int* perm;
+    double* Zs;         // [n][n], columns in rank order
+    int n, rows;        // rows per workgroup (= threads)
+};
+
+// Each lane owns one row of Z, stored column-major in LDS (word col * rows + lane).  A QL
+// sweep applies rotations on planes i, i-1, i-2, ...: the column shared by consecutive
+// planes stays in a register, and the next plane's other column is loaded before the
+// current plane's result is stored (it is a different column), so the LDS latency is
+// off the dependency chain.
+__global__ void __launch_bounds__(64) replay_kernel(const ReplayArgs a) {
+    extern __shared__ double zl[];
+    const int n = a.n, R = a.rows, lane = threadIdx.x;
+    const int row = blockIdx.x * R + lane;
+    const bool live = lane < R && row < n;
+    if (lane < R)
+        for (int col = 0; col < n; ++col) zl[col * R + lane] = (col == row) ? 1.0 : 0.0;
+    __syncthreads();
+    const int cnt = *a.rot_n;
+    if (cnt > 0 && lane < R) {
+        double* z = zl + lane;
+        int i = a.rot_i[0];
+        double c = a.rot_c[0], s = a.rot_s[0];
+        double av = z[i * R], bv = z[(i + 1) * R];
+        for (int k = 0; k < cnt; ++k) {
+            const bool more = k + 1 < cnt;
+            const int in = more ? a.rot_i[k + 1] : -2;
+            const double cn = more ? a.rot_c[k + 1] : 0.0, sn = more ? a.rot_s[k + 1] : 0.0;
+            const bool cont = in == i - 1;
+            const double pre = cont ? z[in * R] : 0.0;   // column i-1, untouched by plane i
+            const double na = c * av - s * bv;
+            const double nb = s * av + c * bv;
+            z[(i + 1) * R] = nb;
+            if (cont) {
+                bv = na;
+                av = pre;
+            } else {
+                z[i * R] = na;
+                if (more) {
+                    av = z[in * R];
+                    bv = z[(in + 1) * R];
+                }
+            }
+            i = in;
+            c = cn;
+            s = sn;
+        }
+    }
+    __syncthreads();
+    if (live)
+        for (int j = 0; j < n; ++j) a.Zs[(size_t)row * n + j] = zl[a.perm[j] * R + lane];
+}
+
+// ------------------------------------------------------------------ 4. back-transformation
+struct BackArgs {
+    const double* Zs;     // [n][n]
+    const double2* vh;    // [n][n]
+    const double2* tau;   // [n]
+    double2* V;           // [n][n], columns 0 .. ncols-1 written
+    int n;
+};
+
+constexpr int BT_PER_LANE = FQ_MAX_NT / 64;
+
+__global__ void __launch_bounds__(64) back_kernel(const BackArgs a) {
+    const int n = a.n, j = blockIdx.x, lane = threadIdx.x;
+    double2 z[BT_PER_LANE];
+#pragma unroll
+    for (int t = 0; t < BT_PER_LANE; ++t) {
+        const int i = lane + 64 * t;
+        z[t] = make_double2(i < n ? a.Zs[(size_t)i * n + j] : 0.0, 0.0);
+    }
+    for (int k = n - 2; k >= 0; --k) {
+        const double2 tau = a.tau[k];
+        if (tau.x == 0.0 && tau.y == 0.0) continue;
+        const double2* v = a.vh + (size_t)k * n;
+        double2 dot = make_double2(0.0, 0.0);   // v^H z over rows k+1 .. n-1
+#pragma unroll
+        for (int t = 0; t < BT_PER_LANE; ++t) {
+            const int i = lane + 64 * t;
+            if (i > k && i < n) {
+                const double2 vi = v[i];
+                dot.x += vi.x * z[t].x + vi.y * z[t].y;
+                dot.y += vi.x * z[t].y - vi.y * z[t].x;
+            }
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+            dot.x += __shfl_xor(dot.x, o);
+            dot.y += __shfl_xor(dot.y, o);
+        }
+        const double2 td = zmul(tau, dot);
+#pragma unroll
+        for (int t = 0; t < BT_PER_LANE; ++t) {
+            const int i = lane + 64 * t;
+            if (i > k && i < n) {
+                const double2 u = zmul(v[i], td);
+                z[t].x -= u.x;
+                z[t].y -= u.y;
+            }
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < BT_PER_LANE; ++t) {
+        const int i = lane + 64 * t;
+        if (i < n) a.V[(size_t)i * n + j] = z[t];
+    }
 }
 
 // K selection and FP32 copy of V_K (one workgroup).
@@ -299,45 +497,68 @@ __global__ void __launch_bounds__(256) pd_kernel(const float2* iq, int64_t nv, i
 }
 
 struct SvdWs {
-    size_t off_A, off_V, off_lam, off_vecs, off_vk, off_k, total;
+    size_t off_A, off_vh, off_tau, off_d, off_e, off_ri, off_rc, off_rs, off_rn, off_perm, off_Zs;
+    size_t off_lam, off_vecs, off_vk, off_k, total;
+    int cap;
 };
 
 SvdWs svd_layout(int n) {
-    const int m = n + (n & 1);
     SvdWs w{};
     size_t o = 0;
-    w.off_A = o;
-    o += round_up(sizeof(double2) * (size_t)m * m, 256);
-    w.off_V = o;
-    o += round_up(sizeof(double2) * (size_t)m * m, 256);
-    w.off_lam = o;
-    o += round_up(sizeof(double) * (size_t)n, 256);
-    w.off_vecs = o;
-    o += round_up(sizeof(double2) * (size_t)n * n, 256);
-    w.off_vk = o;
-    o += round_up(sizeof(float2) * (size_t)n * KMAX, 256);
-    w.off_k = o;
-    o += 256;
+    auto take = [&](size_t bytes) {
+        const size_t at = o;
+        o += round_up(bytes, 256);
+        return at;
+    };
+    const size_t nn = (size_t)n * n;
+    w.cap = ROT_PER_N2 * n * n + 64;
+    w.off_A = take(sizeof(double2) * nn);
+    w.off_vh = take(sizeof(double2) * nn);
+    w.off_tau = take(sizeof(double2) * n);
+    w.off_d = take(sizeof(double) * n);
+    w.off_e = take(sizeof(double) * n);
+    w.off_ri = take(sizeof(int) * (size_t)w.cap);
+    w.off_rc = take(sizeof(double) * (size_t)w.cap);
+    w.off_rs = take(sizeof(double) * (size_t)w.cap);
+    w.off_rn = take(sizeof(int));
+    w.off_perm = take(sizeof(int) * n);
+    w.off_Zs = take(sizeof(double) * nn);
+    w.off_lam = take(sizeof(double) * n);
+    w.off_vecs = take(sizeof(double2) * nn);
+    w.off_vk = take(sizeof(float2) * (size_t)n * KMAX);
+    w.off_k = take(sizeof(int));
     w.total = o;
     return w;
 }
 
+// Eigenvalues (descending, clamped) into lam/sigma; the leading ncols eigenvectors into
+// vecs ([n][n] complex128, columns in rank order) unless vecs is null.
 int launch_eig(const double* gram, int n, char* ws, const SvdWs& L, double* lam, double* sigma, double* vecs,
-               int* status, hipStream_t s) {
-    EigArgs ea{};
-    ea.G = reinterpret_cast<const double2*>(gram);
-    ea.A = reinterpret_cast<double2*>(ws + L.off_A);
-    ea.V = reinterpret_cast<double2*>(ws + L.off_V);
-    ea.lam = lam;
-    ea.sigma = sigma;
-    ea.vecs = reinterpret_cast<double2*>(vecs);
-    ea.status = status;
-    ea.n = n;
-    ea.m = n + (n & 1);
-    ea.max_sweeps = 60;
-    ea.tol = 1e-14;
-    if (ea.m < 2) ea.m = 2;
-    hipLaunchKernelGGL(jacobi_kernel, dim3(1), dim3(EIG_THREADS), 0, s, ea);
+               int ncols, int* status, hipStream_t s) {
+    double2* vh = reinterpret_cast<double2*>(ws + L.off_vh);
+    double2* tau = reinterpret_cast<double2*>(ws + L.off_tau);
+    double* d = reinterpret_cast<double*>(ws + L.off_d);
+    double* e = reinterpret_cast<double*>(ws + L.off_e);
+    int* ri = reinterpret_cast<int*>(ws + L.off_ri);
+    double* rc = reinterpret_cast<double*>(ws + L.off_rc);
+    double* rs = reinterpret_cast<double*>(ws + L.off_rs);
+    int* rn = reinterpret_cast<int*>(ws + L.off_rn);
+    int* perm = reinterpret_cast<int*>(ws + L.off_perm);
+    double* Zs = reinterpret_cast<double*>(ws + L.off_Zs);
+
+    TriArgs ta{reinterpret_cast<const double2*>(gram), reinterpret_cast<double2*>(ws + L.off_A), vh, tau, d, e, n};
+    hipLaunchKernelGGL(tridiag_kernel, dim3(1), dim3(TRI_THREADS), 0, s, ta);
+    FQ_LAUNCH_CHECK();
+    QlArgs qa{d, e, ri, rc, rs, rn, L.cap, lam, sigma, perm, status, n};
+    hipLaunchKernelGGL(ql_kernel, dim3(1), dim3(64), 0, s, qa);
+    FQ_LAUNCH_CHECK();
+    if (!vecs || ncols < 1) return FQ_OK;
+    const int rows = n <= 256 ? 64 : 32;   // LDS: rows x n doubles <= 128 KiB
+    ReplayArgs pa{ri, rc, rs, rn, perm, Zs, n, rows};
+    hipLaunchKernelGGL(replay_kernel, dim3((n + rows - 1) / rows), dim3(64), sizeof(double) * (size_t)rows * n, s, pa);
+    FQ_LAUNCH_CHECK();
+    BackArgs ba{Zs, vh, tau, reinterpret_cast<double2*>(vecs), n};
+    hipLaunchKernelGGL(back_kernel, dim3(std::min(ncols, n)), dim3(64), 0, s, ba);
     FQ_LAUNCH_CHECK();
     return FQ_OK;
 }
@@ -359,19 +580,19 @@ using namespace fq;
 extern "C" size_t svd_workspace_size(int64_t n_vox, int32_t n_t) {
     (void)n_vox;
     if (n_t < 1) return 0;
-    return svd_layout(std::max(n_t, 2)).total;
+    return svd_layout(n_t).total;
 }
 
 extern "C" int hermitian_eig(const double* gram, int32_t n_t, void* ws, size_t ws_bytes, double* lam, double* vecs,
                              int32_t* status, void* stream) {
     FQ_REQUIRE(n_t >= 1 && n_t <= FQ_MAX_NT, "n_t must be 1..%d", FQ_MAX_NT);
     FQ_REQUIRE(gram && ws && lam && aligned16(gram) && aligned16(ws), "null or misaligned pointer");
-    const SvdWs L = svd_layout(std::max(n_t, 2));
+    const SvdWs L = svd_layout(n_t);
     if (ws_bytes < L.total) {
         set_error("workspace too small: %zu < %zu bytes", ws_bytes, L.total);
         return FQ_E_WORKSPACE;
     }
-    return launch_eig(gram, n_t, reinterpret_cast<char*>(ws), L, lam, nullptr, vecs, status, as_stream(stream));
+    return launch_eig(gram, n_t, reinterpret_cast<char*>(ws), L, lam, nullptr, vecs, n_t, status, as_stream(stream));
 }
 
 extern "C" int svd_clutter_filter(const float* iq, int64_t n_vox, int32_t n_t, const double* gram, int32_t cutoff,
@@ -384,7 +605,7 @@ extern "C" int svd_clutter_filter(const float* iq, int64_t n_vox, int32_t n_t, c
     FQ_REQUIRE(iq && gram && ws && sigma && k_used && aligned16(iq) && aligned16(gram) && aligned16(ws),
                "null or misaligned pointer");
     FQ_REQUIRE(!iq_filt || aligned16(iq_filt), "misaligned iq_filt");
-    const SvdWs L = svd_layout(std::max(n_t, 2));
+    const SvdWs L = svd_layout(n_t);
     if (ws_bytes < L.total) {
         set_error("workspace too small: %zu < %zu bytes", ws_bytes, L.total);
         return FQ_E_WORKSPACE;
@@ -393,7 +614,7 @@ extern "C" int svd_clutter_filter(const float* iq, int64_t n_vox, int32_t n_t, c
     char* w = reinterpret_cast<char*>(ws);
     double* lam = reinterpret_cast<double*>(w + L.off_lam);
     double* vecs = reinterpret_cast<double*>(w + L.off_vecs);
-    int st = launch_eig(gram, n_t, w, L, lam, sigma, vecs, status, s);
+    int st = launch_eig(gram, n_t, w, L, lam, sigma, vecs, std::min(n_t, KMAX), status, s);
     if (st != FQ_OK) return st;
     RankArgs ra{lam, reinterpret_cast<const double2*>(vecs), reinterpret_cast<float2*>(w + L.off_vk), k_used, status,
                 n_t, cutoff};
