@@ -215,20 +215,30 @@ __global__ void __launch_bounds__(64) ql_kernel(const QlArgs a) {
                 double s = 1.0, c = 1.0, p = 0.0;
                 int i = m - 1;
                 bool split = false;
+                // d[i], d[i+1], e[i] of the current plane; the next plane's e and d are
+                // read one step ahead (this step writes only e[i+1] and d[i+1])
+                double ei = e[i], di = d[i], dip1 = d[i + 1];
                 for (; i >= l; --i) {
-                    const double f = s * e[i], b = c * e[i];
-                    r = sqrt(f * f + g * g);
-                    e[i + 1] = r;
-                    if (r == 0.0) {   // e[i] vanished: the block splits, restart
-                        d[i + 1] -= p;
+                    const int inx = i > 0 ? i - 1 : 0;   // clamped: read unconditionally
+                    const double e_nx = e[inx], d_nx = d[inx];
+                    const double f = s * ei, b = c * ei;
+                    const double x = f * f + g * g;
+                    if (x == 0.0) {   // e[i] vanished: the block splits, restart
+                        e[i + 1] = 0.0;
+                        d[i + 1] = dip1 - p;
                         e[m] = 0.0;
                         split = true;
                         break;
                     }
-                    s = f / r;
-                    c = g / r;
-                    g = d[i + 1] - p;
-                    r = (d[i] - g) * s + 2.0 * c * b;
+                    // 1/sqrt(x) from the hardware estimate and two Newton steps
+                    double y = __builtin_amdgcn_rsq(x);
+                    y = y * fma(-0.5 * x * y, y, 1.5);
+                    y = y * fma(-0.5 * x * y, y, 1.5);
+                    e[i + 1] = x * y;
+                    s = f * y;
+                    c = g * y;
+                    g = dip1 - p;
+                    r = (di - g) * s + 2.0 * c * b;
                     p = s * r;
                     d[i + 1] = g + p;
                     g = c * r - b;
@@ -236,6 +246,9 @@ __global__ void __launch_bounds__(64) ql_kernel(const QlArgs a) {
                     a.rot_c[cnt] = c;
                     a.rot_s[cnt] = s;
                     ++cnt;
+                    ei = e_nx;
+                    dip1 = di;
+                    di = d_nx;
                 }
                 if (split) continue;
                 d[l] -= p;
@@ -272,47 +285,64 @@ struct ReplayArgs {
     int n, rows;        // rows per workgroup (= threads)
 };
 
-// Each lane owns one row of Z, stored column-major in LDS (word col * rows + lane).  A QL
-// sweep applies rotations on planes i, i-1, i-2, ...: the column shared by consecutive
-// planes stays in a register, and the next plane's other column is loaded before the
-// current plane's result is stored (it is a different column), so the LDS latency is
-// off the dependency chain.
+// Each lane owns one row of Z, stored column-major in LDS (word col * rows + lane).  The
+// rotation log is staged through LDS in chunks and read two rotations ahead.  A QL sweep
+// applies rotations on planes i, i-1, i-2, ...: the column shared by consecutive planes
+// stays in a register, and the next plane's other column is loaded before the current
+// plane's result is stored (it is a different column), so the LDS latency is off the
+// dependency chain.
+constexpr int RCH = 1024;   // rotations per staged chunk
+
 __global__ void __launch_bounds__(64) replay_kernel(const ReplayArgs a) {
     extern __shared__ double zl[];
+    __shared__ int ri_s[RCH + 2];   // two sentinel planes (-1) after the chunk
+    __shared__ double rc_s[RCH + 2], rs_s[RCH + 2];
     const int n = a.n, R = a.rows, lane = threadIdx.x;
     const int row = blockIdx.x * R + lane;
     const bool live = lane < R && row < n;
     if (lane < R)
         for (int col = 0; col < n; ++col) zl[col * R + lane] = (col == row) ? 1.0 : 0.0;
-    __syncthreads();
     const int cnt = *a.rot_n;
-    if (cnt > 0 && lane < R) {
-        double* z = zl + lane;
-        int i = a.rot_i[0];
-        double c = a.rot_c[0], s = a.rot_s[0];
+    double* z = zl + (lane < R ? lane : 0);
+    for (int base = 0; base < cnt; base += RCH) {
+        const int nch = min(RCH, cnt - base);
+        __syncthreads();
+        for (int t = lane; t < nch + 2; t += 64) {
+            const bool in = t < nch;
+            ri_s[t] = in ? a.rot_i[base + t] : -1;
+            rc_s[t] = in ? a.rot_c[base + t] : 1.0;
+            rs_s[t] = in ? a.rot_s[base + t] : 0.0;
+        }
+        __syncthreads();
+        if (lane >= R) continue;
+        int i = ri_s[0];
+        double c = rc_s[0], s = rs_s[0];
+        int i1 = ri_s[1];
+        double c1 = rc_s[1], s1 = rs_s[1];
         double av = z[i * R], bv = z[(i + 1) * R];
-        for (int k = 0; k < cnt; ++k) {
-            const bool more = k + 1 < cnt;
-            const int in = more ? a.rot_i[k + 1] : -2;
-            const double cn = more ? a.rot_c[k + 1] : 0.0, sn = more ? a.rot_s[k + 1] : 0.0;
-            const bool cont = in == i - 1;
-            const double pre = cont ? z[in * R] : 0.0;   // column i-1, untouched by plane i
+        for (int k = 0; k < nch; ++k) {
+            // rotation k+2 is fetched now (sentinels past the end), k+1 is in registers
+            const int i2 = ri_s[k + 2];
+            const double c2 = rc_s[k + 2], s2 = rs_s[k + 2];
+            const int i1c = i1 > 0 ? i1 : 0;
+            const double pre = z[i1c * R];   // column i-1 when the sweep continues (untouched here)
             const double na = c * av - s * bv;
             const double nb = s * av + c * bv;
             z[(i + 1) * R] = nb;
-            if (cont) {
+            z[i * R] = na;
+            if (i1 == i - 1) {   // same sweep: plane i-1 shares column i
                 bv = na;
                 av = pre;
-            } else {
-                z[i * R] = na;
-                if (more) {
-                    av = z[in * R];
-                    bv = z[(in + 1) * R];
-                }
+            } else if (i1 >= 0) {   // new sweep: read both columns after the stores above
+                av = z[i1 * R];
+                bv = z[(i1 + 1) * R];
             }
-            i = in;
-            c = cn;
-            s = sn;
+            i = i1;
+            c = c1;
+            s = s1;
+            i1 = i2;
+            c1 = c2;
+            s1 = s2;
         }
     }
     __syncthreads();
