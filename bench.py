@@ -162,9 +162,15 @@ def rf_only(cfg, args, fq, torch, dev):
     b_pos, b_amp = torch.from_numpy(sc.blood_pos).to(dev), torch.from_numpy(sc.blood_amp).to(dev)
     rf = torch.empty((acq.n_frames, acq.n_angles, acq.n_elem, acq.n_samples), dtype=torch.float32, device=dev)
 
+    all_pos = None if sc.tissue_static else torch.cat([t_pos, b_pos], dim=1).contiguous()
+    all_amp = None if sc.tissue_static else torch.cat([t_amp, b_amp]).contiguous()
+
     def run():
-        fq.rf_synth(probe, tx, pulse, t_pos, t_amp, rf, pos_static=sc.tissue_static, accumulate=False)
-        fq.rf_synth(probe, tx, pulse, b_pos, b_amp, rf, pos_static=False, accumulate=True)
+        if sc.tissue_static:
+            fq.rf_synth(probe, tx, pulse, t_pos, t_amp, rf, pos_static=True, accumulate=False)
+            fq.rf_synth(probe, tx, pulse, b_pos, b_amp, rf, pos_static=False, accumulate=True)
+        else:
+            fq.rf_synth(probe, tx, pulse, all_pos, all_amp, rf, pos_static=False, accumulate=False)
 
     for _ in range(args.warmup):
         run()
@@ -225,6 +231,9 @@ def main():
     b_pos = torch.from_numpy(sc.blood_pos).to(dev)
     b_amp = torch.from_numpy(sc.blood_amp).to(dev)
     t_static = sc.tissue_static
+    # moving tissue and blood share the frame axis: one synthesis call over both
+    all_pos = None if t_static else torch.cat([t_pos, b_pos], dim=1).contiguous()
+    all_amp = None if t_static else torch.cat([t_amp, b_amp]).contiguous()
 
     rf = torch.empty((F, A, E, T), dtype=torch.float32, device=dev)
     das_ws = torch.empty(fq.das_workspace_size(probe, tx, F, T), dtype=torch.uint8, device=dev)
@@ -270,8 +279,11 @@ def main():
     def step(record: bool):
         if record:
             ev[0].record()
-        fq.rf_synth(probe, tx, pulse, t_pos, t_amp, rf, pos_static=t_static, accumulate=False)
-        fq.rf_synth(probe, tx, pulse, b_pos, b_amp, rf, pos_static=False, accumulate=True)
+        if t_static:
+            fq.rf_synth(probe, tx, pulse, t_pos, t_amp, rf, pos_static=True, accumulate=False)
+            fq.rf_synth(probe, tx, pulse, b_pos, b_amp, rf, pos_static=False, accumulate=True)
+        else:
+            fq.rf_synth(probe, tx, pulse, all_pos, all_amp, rf, pos_static=False, accumulate=False)
         if record:
             ev[1].record()
         fq.das_demodulate(probe, tx, rf, das_ws)

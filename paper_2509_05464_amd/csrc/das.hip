@@ -151,16 +151,17 @@ __global__ void __launch_bounds__(DAS_THREADS) das_kernel(const DasArgs a) {
         __syncthreads();
         // stage W rows per angle; rows outside [0, T) are zero (zero padding)
         const int per_ang = a.W * 4;
-        for (int i = threadIdx.x; i < AT * per_ang; i += DAS_THREADS) {
-            const int j = i / per_ang, rem = i - j * per_ang;
-            const int r = rem >> 2, c4 = rem & 3;
-            const int n = nlo_s[j] + r;
-            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (n >= 0 && n < a.T) {
-                const int64_t tr = ((int64_t)fbl * a.A + a.a0 + j) * a.E + e;
-                v = a.bb[(tr * trace_rows + n) * 4 + c4];
+#pragma unroll
+        for (int j = 0; j < AT; ++j) {
+            const int64_t tr = ((int64_t)fbl * a.A + a.a0 + j) * a.E + e;
+            const float4* src = a.bb + tr * trace_rows * 4;
+            for (int rem = threadIdx.x; rem < per_ang; rem += DAS_THREADS) {
+                const int r = rem >> 2, c4 = rem & 3;
+                const int n = nlo_s[j] + r;
+                float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (n >= 0 && n < a.T) v = src[(int64_t)n * 4 + c4];
+                win[(j * a.W + r) * ROW_F4 + c4] = v;
             }
-            win[(j * a.W + r) * ROW_F4 + c4] = v;
         }
         __syncthreads();
 

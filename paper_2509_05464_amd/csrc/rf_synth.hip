@@ -80,7 +80,12 @@ __device__ __forceinline__ bool make_rec(const RfArgs& a, const float* posf, int
                                          double ux, double uy, double uz, double t0s, Rec& r) {
     const double px = posf[3 * s], py = posf[3 * s + 1], pz = posf[3 * s + 2];
     const double dx = px - pex, dy = py - pey;
-    const double rho = sqrt(dx * dx + dy * dy + pz * pz);
+    const double rr = dx * dx + dy * dy + pz * pz;
+    // receive distance: hardware 1/sqrt estimate, then one Newton step in FP64 (relative
+    // error ~1e-14, i.e. ~1e-11 samples of delay)
+    const double yi = __builtin_amdgcn_rsq(rr);
+    double rho = rr * yi;
+    rho = fma(fma(-rho, rho, rr), 0.5 * yi, rho);
     const double x = (ux * px + uy * py + uz * pz) * a.fs_c - t0s + rho * a.fs_c;
     if (!(x > -(double)(J + 2) && x < (double)(a.T + J + 1))) return false;   // also rejects NaN
     const double fl = floor(x);
@@ -90,9 +95,11 @@ __device__ __forceinline__ bool make_rec(const RfArgs& a, const float* posf, int
     r.mhi = fd >= 1.0 - a.h ? 1.0f : 0.0f;
     const float f = (float)fd;
     const float scale = a.amp[s] * a.r_ref * __builtin_amdgcn_rcpf((float)rho);
-    const float gc = scale * exp2f(a.kexp2 * f * f);
-    const float rh = exp2f(-2.0f * a.kexp2 * f);        // rho = exp(f / s^2) >= 1
-    const float rhi = exp2f(2.0f * a.kexp2 * f);        // 1 / rho
+    // exponent arguments lie in [-1/(2 s^2 ln 2), 1/(s^2 ln 2)], far from over/underflow:
+    // the bare hardware exp2 is enough
+    const float gc = scale * __builtin_amdgcn_exp2f(a.kexp2 * f * f);
+    const float rh = __builtin_amdgcn_exp2f(-2.0f * a.kexp2 * f);   // rho = exp(f / s^2) >= 1
+    const float rhi = __builtin_amdgcn_exp2f(2.0f * a.kexp2 * f);   // 1 / rho
     r.e0 = gc * __builtin_amdgcn_cosf(a.nu * f);                 // cos(theta f), argument in turns
     r.e1 = gc * rh * __builtin_amdgcn_cosf(a.nu * (1.0f - f));   // rho cos(theta (1 - f))
     r.af = a.two_cos_theta * rh;
