@@ -29,6 +29,14 @@ if ROOT not in sys.path:
 PEAK_FP32_FMA_TFLOPS = 78.6      # 256 CU x 4 SIMD x 16 lanes x 2 FLOP x 2.4 GHz, FP32 FMA without packed math
 PEAK_FP32_PACKED_TFLOPS = 157.3  # published FP32 vector peak (needs packed FP32 instructions)
 DAS_FLOP_PER_UNIT = 16           # two complex multiply-adds per voxel*element*angle*frame (linear)
+RF_FLOP_PER_TAP = 5              # per pulse sample: recurrence multiply + FMA, accumulate FMA
+
+
+def rf_taps(acq, n_scat: int) -> float:
+    """Pulse samples one RF synthesis of n_scat scatterers evaluates: per (scatterer, element,
+    transmit, frame) the samples with |n - x| <= 5 sigma, 2 * 5 sigma on average."""
+    sig = 2.0 / (2.0 * np.sqrt(2.0 * np.log(2.0)) * acq.fc) * acq.fs
+    return float(n_scat) * acq.n_elem * acq.n_angles * acq.n_frames * 2.0 * 5.0 * sig
 
 
 def _log(*a):
@@ -164,6 +172,10 @@ def rf_only(cfg, args, fq, torch, dev):
 
     all_pos = None if sc.tissue_static else torch.cat([t_pos, b_pos], dim=1).contiguous()
     all_amp = None if sc.tissue_static else torch.cat([t_amp, b_amp]).contiguous()
+    src = torch.zeros(1 << 31, dtype=torch.uint8, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)                      # calibration copy: 2 GiB read + 2 GiB written
+    del src, dst
 
     def run():
         if sc.tissue_static:
@@ -182,9 +194,12 @@ def rf_only(cfg, args, fq, torch, dev):
     e1.record()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / args.steps
-    n_rec = (sc.tissue_amp.size + sc.blood_amp.size) * acq.n_elem * acq.n_angles * acq.n_frames
+    n_scat = sc.tissue_amp.size + sc.blood_amp.size
+    n_rec = n_scat * acq.n_elem * acq.n_angles * acq.n_frames
+    taps = rf_taps(acq, n_scat)
     print(json.dumps({'kernel': 'rf_synth_kernel', 'workload': cfg.name, 'ms_per_step': ms,
-                      'records_per_s': n_rec / (ms / 1e3)}))
+                      'records_per_s': n_rec / (ms / 1e3), 'gtaps_per_s': taps / (ms / 1e3) / 1e9,
+                      'tflops': RF_FLOP_PER_TAP * taps / (ms / 1e3) / 1e12}))
 
 
 def main():
@@ -334,8 +349,11 @@ def main():
     ms_step = wall / args.steps * 1e3
     stage_ms = {s: float(v / args.steps) for s, v in zip(stages, acc)}
     units = acq.das_units()
-    t_das = stage_ms['das'] / 1e3
+    stage_ms_das = stage_ms['das']
+    t_das = stage_ms_das / 1e3
     achieved = DAS_FLOP_PER_UNIT * units / t_das / 1e12
+    stage_ms_rf = stage_ms['rf_synth']
+    rf_achieved = RF_FLOP_PER_TAP * rf_taps(acq, sc.tissue_amp.size + sc.blood_amp.size) / (stage_ms_rf / 1e3) / 1e12
 
     out = {
         'metric': 'DAS Gvoxel*element*angle/s (whole step: RF synthesis, DAS, SVD and learned clutter filters, PD)',
@@ -357,16 +375,33 @@ def main():
                          f'cutoff {"knee" if cfg.cutoff < 0 else cfg.cutoff}'),
             'das_units_per_step': units,
         },
-        'roofline': {
-            'bound': 'alu',
-            'kernel': 'das_kernel (delay-and-sum, linear interpolation)',
-            'achieved': achieved,
-            'peak': PEAK_FP32_FMA_TFLOPS,
-            'unit': 'TFLOP/s',
-            'frac': achieved / PEAK_FP32_FMA_TFLOPS,
-            'frac_vs_packed_fp32_peak': achieved / PEAK_FP32_PACKED_TFLOPS,
-            'traffic': measured_traffic('das_kernel_c2_hbm_traffic.md') if cfg.name in ('c2', 'c3') else None,
-            'traffic_unit': 'bytes per launch (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, copy-calibrated)',
+        'roofline': None,   # the dominant kernel's entry of `rooflines`, set below
+        'rooflines': {
+            'das_kernel': {
+                'bound': 'alu',
+                'work': 'delay-and-sum, linear interpolation: 16 FLOP per voxel*element*angle*frame',
+                'achieved': achieved,
+                'peak': PEAK_FP32_FMA_TFLOPS,
+                'unit': 'TFLOP/s',
+                'frac': achieved / PEAK_FP32_FMA_TFLOPS,
+                'frac_vs_packed_fp32_peak': achieved / PEAK_FP32_PACKED_TFLOPS,
+                'traffic': measured_traffic('das_kernel_c2_hbm_traffic.md') if cfg.name in ('c2', 'c3') else None,
+                'traffic_unit': 'bytes per launch (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, copy-calibrated)',
+                'stage_ms': stage_ms_das,
+            },
+            'rf_synth_kernel': {
+                'bound': 'alu',
+                'work': 'pulse samples (|n - x| <= 5 sigma) of every scatterer*element*angle*frame: '
+                        f'{RF_FLOP_PER_TAP} FLOP each',
+                'achieved': rf_achieved,
+                'peak': PEAK_FP32_FMA_TFLOPS,
+                'unit': 'TFLOP/s',
+                'frac': rf_achieved / PEAK_FP32_FMA_TFLOPS,
+                'frac_vs_packed_fp32_peak': rf_achieved / PEAK_FP32_PACKED_TFLOPS,
+                'traffic': measured_traffic('rf_synth_c2_hbm_traffic.md') if cfg.name in ('c2', 'c3') else None,
+                'traffic_unit': 'bytes per launch (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, copy-calibrated)',
+                'stage_ms': stage_ms_rf,
+            },
         },
         'stage_ms': stage_ms,
         'das_gunits_per_s': units / t_das / 1e9,
@@ -380,6 +415,9 @@ def main():
         'k_used': {'svd_fp32': int(k1.item()), 'svd_split4_bf16': int(k2.item())},
         'eig_status': {'svd_fp32': int(st1.item()), 'svd_split4_bf16': int(st2.item())},
     }
+
+    dominant = 'rf_synth_kernel' if stage_ms_rf > stage_ms_das else 'das_kernel'
+    out['roofline'] = dict(out['rooflines'][dominant], kernel=dominant)
 
     if not args.no_truth:
         # untimed: ground-truth blood PD (DAS of blood-only RF) and each path's error
