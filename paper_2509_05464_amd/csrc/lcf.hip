@@ -47,6 +47,26 @@ __device__ __forceinline__ unsigned short f2bf(float x) {
 }
 __device__ __forceinline__ float bf2f(unsigned short b) { return __uint_as_float((unsigned int)b << 16); }
 __device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
+// GELU for the forward pass, whose result is rounded to BF16: erf by formula 7.1.26 of
+// Abramowitz & Stegun (Handbook of Mathematical Functions), |error| <= 1.5e-7, i.e.
+// erf(x) = 1 - t (a1 + t (a2 + t (a3 + t (a4 + t a5)))) exp(-x^2), t = 1/(1 + p x), x >= 0.
+__device__ __forceinline__ float gelu_fwd(float z) {
+    const float x = fabsf(z) * 0.70710678118654752f;
+    const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f, x, 1.0f));
+    float poly = fmaf(1.061405429f, t, -1.453152027f);
+    poly = fmaf(poly, t, 1.421413741f);
+    poly = fmaf(poly, t, -0.284496736f);
+    poly = fmaf(poly, t, 0.254829592f);
+    const float q = poly * t * __builtin_amdgcn_exp2f(-1.4426950408889634f * x * x);   // 1 - erf(x)
+    // GELU = z (1 + sign(z) erf(|z|/sqrt 2)) / 2
+    return z >= 0.0f ? fmaf(-0.5f * z, q, z) : 0.5f * z * q;
+}
+// two floats to BF16 (round to nearest even) with the hardware pair conversion
+__device__ __forceinline__ unsigned int f2bf2(float lo, float hi) {
+    typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+    const bf16x2 v = {(__bf16)lo, (__bf16)hi};
+    return __builtin_bit_cast(unsigned int, v);
+}
 __device__ __forceinline__ float gelu_grad(float z) {
     return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) + z * 0.39894228040143268f * expf(-0.5f * z * z);
 }
@@ -208,20 +228,20 @@ __global__ void __launch_bounds__(64) lcf_fwd_kernel(const FwdArgs a) {
                 for (int tt = 0; tt < g.TT; ++tt) {
                     const floatx16 acc = layer == 1 ? conv8(h0, 32 * tt, f1, l) : conv32(ha, 32 * tt, f2, l);
                     const int t = 32 * tt + j;
+                    const bool live = t < g.T;
 #pragma unroll
                     for (int q = 0; q < 4; ++q) {
                         const int o = 8 * q + 4 * h;
-                        u16x4 zb, hbv;
+                        float z[4];
 #pragma unroll
-                        for (int p = 0; p < 4; ++p) {
-                            const float z = acc[4 * q + p] + bias[o + p];
-                            zb[p] = f2bf(z);
-                            hbv[p] = t < g.T ? f2bf(gelu(z)) : (unsigned short)0;
-                        }
-                        *reinterpret_cast<u16x4*>(dst + (t + PADT) * CH + o) = hbv;
-                        if (actv && t < g.T) {
-                            *reinterpret_cast<u16x4*>(actv + act_off(2 * layer - 1, g.T) + t * CH + o) = zb;
-                            *reinterpret_cast<u16x4*>(actv + act_off(2 * layer, g.T) + t * CH + o) = hbv;
+                        for (int p = 0; p < 4; ++p) z[p] = acc[4 * q + p] + bias[o + p];
+                        uint2 hv = make_uint2(f2bf2(gelu_fwd(z[0]), gelu_fwd(z[1])), f2bf2(gelu_fwd(z[2]), gelu_fwd(z[3])));
+                        if (!live) hv = make_uint2(0u, 0u);
+                        *reinterpret_cast<uint2*>(dst + (t + PADT) * CH + o) = hv;
+                        if (actv && live) {
+                            const uint2 zv = make_uint2(f2bf2(z[0], z[1]), f2bf2(z[2], z[3]));
+                            *reinterpret_cast<uint2*>(actv + act_off(2 * layer - 1, g.T) + t * CH + o) = zv;
+                            *reinterpret_cast<uint2*>(actv + act_off(2 * layer, g.T) + t * CH + o) = hv;
                         }
                     }
                 }
@@ -236,19 +256,21 @@ __global__ void __launch_bounds__(64) lcf_fwd_kernel(const FwdArgs a) {
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     const int o = 8 * q + 4 * h;
-                    u16x4 zb, hbv;
+                    float z[4];
+#pragma unroll
+                    for (int p = 0; p < 4; ++p) z[p] = acc[4 * q + p] + par[64 + o + p];
+                    const uint2 hv = make_uint2(f2bf2(gelu_fwd(z[0]), gelu_fwd(z[1])), f2bf2(gelu_fwd(z[2]), gelu_fwd(z[3])));
+                    const float hf[4] = {__uint_as_float(hv.x << 16), __uint_as_float(hv.x & 0xffff0000u),
+                                         __uint_as_float(hv.y << 16), __uint_as_float(hv.y & 0xffff0000u)};
 #pragma unroll
                     for (int p = 0; p < 4; ++p) {
-                        const float z = acc[4 * q + p] + par[64 + o + p];
-                        zb[p] = f2bf(z);
-                        hbv[p] = f2bf(gelu(z));
-                        const float hv = bf2f(hbv[p]);
-                        y0 = fmaf(par[96 + o + p], hv, y0);
-                        y1 = fmaf(par[128 + o + p], hv, y1);
+                        y0 = fmaf(par[96 + o + p], hf[p], y0);
+                        y1 = fmaf(par[128 + o + p], hf[p], y1);
                     }
                     if (actv && t < g.T) {
-                        *reinterpret_cast<u16x4*>(actv + act_off(5, g.T) + t * CH + o) = zb;
-                        *reinterpret_cast<u16x4*>(actv + act_off(6, g.T) + t * CH + o) = hbv;
+                        const uint2 zv = make_uint2(f2bf2(z[0], z[1]), f2bf2(z[2], z[3]));
+                        *reinterpret_cast<uint2*>(actv + act_off(5, g.T) + t * CH + o) = zv;
+                        *reinterpret_cast<uint2*>(actv + act_off(6, g.T) + t * CH + o) = hv;
                     }
                 }
                 y0 += __shfl_xor(y0, 32);
