@@ -174,7 +174,7 @@ __global__ void __launch_bounds__(DAS_THREADS) das_kernel(const DasArgs a) {
 #pragma unroll
         for (int k = 0; k < VZ; ++k) {
             const double z = zv0 + k * a.dz;
-            const double rho = sqrt(dxy2 + z * z);
+            const double rho = sqrt_nr(dxy2 + z * z);
             const double xr = rho * a.fs_c;
             const double fl = floor(xr);
             nrx[k] = (int)fl;
@@ -205,27 +205,31 @@ __global__ void __launch_bounds__(DAS_THREADS) das_kernel(const DasArgs a) {
                     w[2] = 0.5f * (-3.0f * a3 + 4.0f * a2 + al);
                     w[3] = 0.5f * (a3 - a2);
                 }
-                // weights folded with the phase: acc += (w_t P) * b_t
-                float2 wp[NT];
-#pragma unroll
-                for (int t = 0; t < NT; ++t) wp[t] = make_float2(w[t] * P.x, w[t] * P.y);
+                // taps combined with the real weights, then rotated: acc += P * sum_t w_t b_t
+                const float nPy = -P.y;
                 const float4* rp = win + (j * a.W + row) * ROW_F4;
 #pragma unroll
                 for (int q = 0; q < FB / 2; ++q) {
+                    const float4 b0 = rp[q];
+                    float4 B = make_float4(w[0] * b0.x, w[0] * b0.y, w[0] * b0.z, w[0] * b0.w);
 #pragma unroll
-                    for (int t = 0; t < NT; ++t) {
+                    for (int t = 1; t < NT; ++t) {
                         const float4 b = rp[t * ROW_F4 + q];
-                        float2& c0 = acc[k][2 * q];
-                        float2& c1 = acc[k][2 * q + 1];
-                        c0.x = fmaf(wp[t].x, b.x, c0.x);
-                        c0.x = fmaf(-wp[t].y, b.y, c0.x);
-                        c0.y = fmaf(wp[t].x, b.y, c0.y);
-                        c0.y = fmaf(wp[t].y, b.x, c0.y);
-                        c1.x = fmaf(wp[t].x, b.z, c1.x);
-                        c1.x = fmaf(-wp[t].y, b.w, c1.x);
-                        c1.y = fmaf(wp[t].x, b.w, c1.y);
-                        c1.y = fmaf(wp[t].y, b.z, c1.y);
+                        B.x = fmaf(w[t], b.x, B.x);
+                        B.y = fmaf(w[t], b.y, B.y);
+                        B.z = fmaf(w[t], b.z, B.z);
+                        B.w = fmaf(w[t], b.w, B.w);
                     }
+                    float2& c0 = acc[k][2 * q];
+                    float2& c1 = acc[k][2 * q + 1];
+                    c0.x = fmaf(P.x, B.x, c0.x);
+                    c0.x = fmaf(nPy, B.y, c0.x);
+                    c0.y = fmaf(P.x, B.y, c0.y);
+                    c0.y = fmaf(P.y, B.x, c0.y);
+                    c1.x = fmaf(P.x, B.z, c1.x);
+                    c1.x = fmaf(nPy, B.w, c1.x);
+                    c1.y = fmaf(P.x, B.w, c1.y);
+                    c1.y = fmaf(P.y, B.z, c1.y);
                 }
             }
         }

@@ -92,12 +92,19 @@ __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
 }
 
 // exp(i 2 pi frac) for the fractional part of a double-precision cycle count; the
-// integer part is removed exactly in FP64 and the remainder is evaluated in FP32.
+// integer part is removed exactly in FP64 and the remainder, in turns, goes to the
+// hardware sine and cosine (which take turns; absolute error ~1e-7).
 __device__ __forceinline__ float2 cis_cycles(double cyc) {
-    double fr = cyc - floor(cyc);
-    float s, c;
-    sincospif(2.0f * (float)fr, &s, &c);
-    return make_float2(c, s);
+    const float fr = (float)(cyc - floor(cyc));
+    return make_float2(__builtin_amdgcn_cosf(fr), __builtin_amdgcn_sinf(fr));
+}
+
+// sqrt(x) for x > 0 from the hardware 1/sqrt estimate and one FP64 Newton step
+// (relative error ~1e-14).
+__device__ __forceinline__ double sqrt_nr(double x) {
+    const double y = __builtin_amdgcn_rsq(x);
+    const double r = x * y;
+    return fma(fma(-r, r, x), 0.5 * y, r);
 }
 
 }  // namespace fq

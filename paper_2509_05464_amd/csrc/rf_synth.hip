@@ -80,12 +80,8 @@ __device__ __forceinline__ bool make_rec(const RfArgs& a, const float* posf, int
                                          double ux, double uy, double uz, double t0s, Rec& r) {
     const double px = posf[3 * s], py = posf[3 * s + 1], pz = posf[3 * s + 2];
     const double dx = px - pex, dy = py - pey;
-    const double rr = dx * dx + dy * dy + pz * pz;
-    // receive distance: hardware 1/sqrt estimate, then one Newton step in FP64 (relative
-    // error ~1e-14, i.e. ~1e-11 samples of delay)
-    const double yi = __builtin_amdgcn_rsq(rr);
-    double rho = rr * yi;
-    rho = fma(fma(-rho, rho, rr), 0.5 * yi, rho);
+    // receive distance (relative error ~1e-14, i.e. ~1e-11 samples of delay)
+    const double rho = sqrt_nr(dx * dx + dy * dy + pz * pz);
     const double x = (ux * px + uy * py + uz * pz) * a.fs_c - t0s + rho * a.fs_c;
     if (!(x > -(double)(J + 2) && x < (double)(a.T + J + 1))) return false;   // also rejects NaN
     const double fl = floor(x);
