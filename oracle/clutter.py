@@ -105,3 +105,41 @@ def projector(V: np.ndarray, K: int) -> np.ndarray:
     """V_K V_K^H (phase-invariant representation of the tissue subspace)."""
     VK = V[:, :K]
     return VK @ VK.conj().T
+
+
+# --------------------------------------------------------------------------- spatial similarity
+# The singular-value analyses of Section 3 (the figures of singular-value curves beside
+# the correlation-coefficient matrices of the absolute values of the left singular
+# vectors) inspect the spatial modes U = S V Sigma^-1.  The correlation coefficient is
+# invariant to the positive scale 1/sigma_k of a column, so the modes are taken as the
+# columns of S V directly.
+
+def spatial_modes_abs(iq: np.ndarray, V: np.ndarray, n_modes: int) -> np.ndarray:
+    """|S V_k| for k < n_modes: float64 [N_v][n_modes]; iq is [N_t][N_v], V [N_t][N_t]."""
+    S = np.asarray(iq, dtype=np.complex128).T                  # [N_v][N_t]
+    return np.abs(S @ np.asarray(V, dtype=np.complex128)[:, :n_modes])
+
+
+def spatial_similarity(iq: np.ndarray, V: np.ndarray, n_modes: int) -> np.ndarray:
+    """Correlation-coefficient matrix [n_modes][n_modes] of the columns of |S V| over voxels."""
+    return np.corrcoef(spatial_modes_abs(iq, V, n_modes), rowvar=False)
+
+
+def ssm_cutoff(C: np.ndarray) -> int:
+    """Tissue rank from the spatial-similarity matrix (no rule is given in the paper,
+    whose cutoff is marked by eye): tissue modes are spatially alike, so the leading
+    block is chosen that best separates inside from outside,
+        score(k) = mean_{i<j<k} C_ij - mean_{i<k<=j} C_ij,   k in [2, M/2],
+    and K = argmax score (first index on ties)."""
+    M = C.shape[0]
+    best_k, best = 2, -np.inf
+    for k in range(2, max(M // 2, 2) + 1):
+        if k >= M:
+            break
+        iu = np.triu_indices(k, 1)
+        inside = C[:k, :k][iu].mean()
+        cross = C[:k, k:].mean()
+        s = inside - cross
+        if s > best:
+            best, best_k = s, k
+    return best_k

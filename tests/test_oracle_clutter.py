@@ -165,3 +165,46 @@ def test_knee_floor_hides_unresolved_tail():
     K = [clutter.knee_cutoff(np.concatenate([head, np.full(30, t)])) for t in (1e-6, 1e-9, 1e-20, 0.0)]
     assert len(set(K)) == 1
     assert K[0] == 6          # the six components above the floor are clutter
+
+
+# ---------------------------------------------------------------- spatial similarity (SSM)
+
+def _unitary(n, rng):
+    q, r = np.linalg.qr(rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n)))
+    return q * (np.diag(r) / np.abs(np.diag(r)))
+
+
+def test_ssm_recovers_designed_spatial_modes():
+    """S = U0 diag(s) V^H with V unitary gives S V = U0 diag(s): the SSM must equal the
+    correlation of the designed magnitudes |U0| (any slip in the projection, e.g. V*
+    instead of V or V^H instead of V, breaks the equality)."""
+    rng = np.random.default_rng(11)
+    nv, nt, m = 3000, 16, 6
+    mag = np.abs(rng.standard_normal((nv, nt))) + 0.1
+    mag[:, 1] = 2.0 * mag[:, 0] + 0.5          # mode 1 an increasing affine copy of mode 0
+    mag[:, 2] = -0.5 * mag[:, 0] + 3.0         # mode 2 a decreasing one
+    U0 = mag * np.exp(2j * np.pi * rng.random((nv, nt)))
+    V = _unitary(nt, rng)
+    s = np.geomspace(100.0, 0.01, nt)
+    S = (U0 * s) @ V.conj().T                  # [N_v][N_t]
+    C = clutter.spatial_similarity(S.T, V, m)
+    want = np.corrcoef(mag[:, :m], rowvar=False)
+    np.testing.assert_allclose(C, want, atol=1e-10)
+    assert abs(C[0, 1] - 1.0) < 1e-12 and abs(C[0, 2] + 1.0) < 1e-12
+    np.testing.assert_allclose(C, C.T, atol=1e-14)
+    np.testing.assert_allclose(np.diag(C), 1.0, atol=1e-14)
+    assert np.all(np.abs(C) <= 1.0 + 1e-12)
+    # the wrong conjugation gives a different matrix
+    Cw = np.corrcoef(np.abs(S @ V.conj()[:, :m]), rowvar=False)
+    assert np.max(np.abs(Cw - want)) > 0.1
+
+
+def test_ssm_cutoff_finds_the_leading_block():
+    M = 20
+    C = np.full((M, M), 0.05)
+    C[:4, :4] = 0.9
+    C[4:9, 4:9] = 0.5
+    np.fill_diagonal(C, 1.0)
+    assert clutter.ssm_cutoff(C) == 4
+    # no block structure: every score ties at zero, the first candidate wins
+    assert clutter.ssm_cutoff(np.eye(M)) == 2
