@@ -92,11 +92,15 @@ def power_doppler(iq: np.ndarray) -> np.ndarray:
 
 
 def svd_filter_pd(iq: np.ndarray, cutoff: int):
-    """Full clutter-filter chain.  cutoff >= 0: fixed K; -1: knee rule.
+    """Full clutter-filter chain.  cutoff >= 0: fixed K; -1: knee rule; -2: rule on the
+    spatial-similarity matrix (ssm_rank).
     Returns (pd float64 [N_v], lam float64 [N_t], V complex128, K)."""
     G = gram(iq)
     lam, V = eig_desc(G)
-    K = knee_cutoff(lam) if cutoff < 0 else int(cutoff)
+    if cutoff == -2:
+        K = ssm_rank(iq, V)
+    else:
+        K = knee_cutoff(lam) if cutoff < 0 else int(cutoff)
     pd = power_doppler(filter_iq(iq, V, K)) if K > 0 else power_doppler(iq)
     return pd, lam, V, K
 
@@ -126,20 +130,28 @@ def spatial_similarity(iq: np.ndarray, V: np.ndarray, n_modes: int) -> np.ndarra
 
 
 def ssm_cutoff(C: np.ndarray) -> int:
-    """Tissue rank from the spatial-similarity matrix (no rule is given in the paper,
-    whose cutoff is marked by eye): tissue modes are spatially alike, so the leading
-    block is chosen that best separates inside from outside,
-        score(k) = mean_{i<j<k} C_ij - mean_{i<k<=j} C_ij,   k in [2, M/2],
-    and K = argmax score (first index on ties)."""
+    """Tissue rank from the spatial-similarity matrix.  The paper marks the cutoff by eye
+    where the leading block of mutually similar modes ends; written here as a membership
+    rule: mode k (0-based, k >= 1) joins the tissue block while its |U| is more alike to
+    the modes before it than to the modes after it,
+        a_k = mean_{i<k} C_ik,   b_k = mean_{k<j<M} C_kj,
+    K = the first k in [1, min(M-2, M/2)] with not (a_k > b_k) (a NaN stops the block);
+    K = max(1, M/2) when every such k joins."""
+    C = np.asarray(C, dtype=np.float64)
     M = C.shape[0]
-    best_k, best = 2, -np.inf
-    for k in range(2, max(M // 2, 2) + 1):
-        if k >= M:
-            break
-        iu = np.triu_indices(k, 1)
-        inside = C[:k, :k][iu].mean()
-        cross = C[:k, k:].mean()
-        s = inside - cross
-        if s > best:
-            best, best_k = s, k
-    return best_k
+    cap = max(1, M // 2)
+    for k in range(1, min(M - 2, cap) + 1):
+        a = C[k, :k].mean()
+        b = C[k, k + 1:].mean()
+        if not a > b:
+            return k
+    return cap
+
+
+SSM_MAX_MODES = 64
+
+
+def ssm_rank(iq: np.ndarray, V: np.ndarray) -> int:
+    """Tissue rank of the clutter filter's SSM mode: the rule above on the leading
+    min(N_t, 64) spatial modes."""
+    return ssm_cutoff(spatial_similarity(iq, V, min(iq.shape[0], SSM_MAX_MODES)))

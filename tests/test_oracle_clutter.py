@@ -199,12 +199,63 @@ def test_ssm_recovers_designed_spatial_modes():
     assert np.max(np.abs(Cw - want)) > 0.1
 
 
-def test_ssm_cutoff_finds_the_leading_block():
-    M = 20
-    C = np.full((M, M), 0.05)
-    C[:4, :4] = 0.9
-    C[4:9, 4:9] = 0.5
+def _block_ssm(M, sizes, levels, background=0.02):
+    """Correlation-like matrix with diagonal blocks of the given sizes and levels."""
+    C = np.full((M, M), background)
+    o = 0
+    for n, lv in zip(sizes, levels):
+        C[o:o + n, o:o + n] = lv
+        o += n
     np.fill_diagonal(C, 1.0)
-    assert clutter.ssm_cutoff(C) == 4
-    # no block structure: every score ties at zero, the first candidate wins
-    assert clutter.ssm_cutoff(np.eye(M)) == 2
+    return C
+
+
+@pytest.mark.parametrize('k_tissue', [1, 2, 3, 5])
+def test_ssm_cutoff_ends_the_leading_block(k_tissue):
+    """A leading block of k modes followed by a second (blood-like) block: the rule
+    returns k, also for a single tissue mode; a block of 1 has no inside pairs."""
+    C = _block_ssm(24, [k_tissue, 6], [0.9, 0.7])
+    assert clutter.ssm_cutoff(C) == k_tissue
+
+
+def test_ssm_cutoff_degenerate_cases():
+    # no similarity anywhere: a_1 = b_1 = 0 is not a join, K = 1
+    assert clutter.ssm_cutoff(np.eye(20)) == 1
+    # a leading block longer than M/2: every candidate joins, K is capped at M/2
+    assert clutter.ssm_cutoff(_block_ssm(20, [15], [0.9])) == 10
+    # all modes equally alike: a_1 = b_1 is not a join
+    assert clutter.ssm_cutoff(np.full((20, 20), 0.8) + 0.2 * np.eye(20)) == 1
+    # tiny matrices
+    assert clutter.ssm_cutoff(np.eye(2)) == 1 and clutter.ssm_cutoff(np.ones((3, 3))) == 1
+    # a NaN correlation (a mode with no spatial variation) enters b_1 or a_1 and stops
+    # the block at its first mode
+    for j in (0, 2, 9):
+        C = _block_ssm(16, [4], [0.9])
+        C[j, :] = np.nan
+        C[:, j] = np.nan
+        assert clutter.ssm_cutoff(C) == 1
+
+
+@pytest.mark.parametrize('k_tissue', [1, 3, 5])
+def test_ssm_rank_recovers_designed_tissue_modes(k_tissue):
+    """S = U0 diag(s) V^H with designed spatial magnitudes: k tissue modes share one
+    smooth footprint over the whole volume, six blood modes share a localised vessel
+    footprint, the rest are independent speckle.  The SSM rule recovers k from S and V."""
+    rng = np.random.default_rng(100 + k_tissue)
+    nv, nt = 4000, 24
+    x = np.arange(nv) / nv
+    tissue = 1.0 + 0.5 * np.sin(2 * np.pi * 7 * x)
+    vessel = np.where((x > 0.25) & (x < 0.35), 1.0, 0.05)
+    mag = np.abs(rng.standard_normal((nv, nt)))
+    for k in range(k_tissue):
+        mag[:, k] = tissue * (1 + 0.1 * rng.standard_normal(nv))
+    for k in range(k_tissue, k_tissue + 6):
+        mag[:, k] = vessel * (1 + 0.1 * rng.standard_normal(nv))
+    mag = np.abs(mag)
+    U0 = mag * np.exp(2j * np.pi * rng.random((nv, nt)))
+    V = _unitary(nt, rng)
+    s = np.geomspace(1e3, 1.0, nt)
+    S = (U0 * s) @ V.conj().T
+    assert clutter.ssm_rank(S.T, V) == k_tissue
+    pd, lam, Vo, K = clutter.svd_filter_pd(S.T, -2)
+    assert K == k_tissue

@@ -69,3 +69,23 @@ def test_static_scene_has_no_power_doppler_after_filter(orc):
     out = pipeline.run(cfg, sc, cutoff=1)
     raw = clutter.power_doppler(out['iq'])
     assert out['pd'].max() < 1e-20 * raw.max()
+
+
+def test_ssm_rank_minimises_blood_pd_error_on_small_scene(orc):
+    """On the small workload (static tissue, one vessel) the tissue rank read from the
+    spatial-similarity matrix is the rank whose power Doppler is closest to the
+    blood-only ground truth (the knee of the singular-value curve is not)."""
+    import dataclasses
+    cfg = get_config('c1')
+    sc = make_scene(cfg)
+    out = pipeline.run(cfg, sc, cutoff=-2)
+    blood = dataclasses.replace(sc, tissue_amp=np.zeros_like(sc.tissue_amp))
+    ref = clutter.power_doppler(pipeline.run(cfg, blood, cutoff=0)['iq'])
+
+    def err_db(K):
+        pd = clutter.power_doppler(clutter.filter_iq(out['iq'], out['V'], K)) if K else clutter.power_doppler(out['iq'])
+        return 10 * np.log10(np.sum((pd - ref) ** 2) / np.sum(ref ** 2))
+
+    errs = [err_db(K) for K in range(7)]
+    assert out['K'] == int(np.argmin(errs))
+    assert errs[out['K']] < -6.0
