@@ -42,10 +42,12 @@ extern "C" {
 
 #define FQ_MAX_ANGLES 32
 #define FQ_MAX_NT 512
+#define FQ_SSM_MAX_MODES 64
 
 enum { FQ_OK = 0, FQ_E_INVALID = 1, FQ_E_WORKSPACE = 2, FQ_E_HIP = 3, FQ_E_NUMERIC = 4 };
 enum { FQ_INTERP_LINEAR = 0, FQ_INTERP_HERMITE = 1 };
 enum { FQ_GRAM_FP32 = 0, FQ_GRAM_SPLIT_BF16 = 1, FQ_GRAM_BF16 = 2, FQ_GRAM_SPLIT4_BF16 = 3 };
+enum { FQ_CUTOFF_KNEE = -1, FQ_CUTOFF_SSM = -2 };
 
 typedef struct {
     int32_t nx_el, ny_el;     /* regular matrix array, nx_el*ny_el elements */
@@ -157,10 +159,12 @@ int casorati_gram(const float* iq, int64_t n_vox, int32_t n_t, int32_t gram_mode
  * svd_clutter_filter -- eigendecomposition of G in FP64 on the GPU (Householder
  * tridiagonalisation, implicit QL, back-transformation), rank selection, projection and
  * power Doppler (Section 2.4.2; Section 3.2 marks the cutoff on the singular-value curve).
- *  cutoff >= 0: K = cutoff; cutoff == -1: knee rule on the dB spectrum
+ *  cutoff >= 0: K = cutoff; cutoff == FQ_CUTOFF_KNEE (-1): knee rule on the dB spectrum
  *     d_k = 10 log10(max(l_k, 1e-6 l_1)/l_1) (floored at -60 dB, the resolution of an
  *     FP32 / split-BF16 Gram), chord l from (1, d_1) to (N, d_N),
- *     k* = argmax_{k in [2, N/2]} (chord_k - d_k) (first on ties), K = clamp(k*-1, 1, N/2-1).
+ *     k* = argmax_{k in [2, N/2]} (chord_k - d_k) (first on ties), K = clamp(k*-1, 1, N/2-1);
+ *  cutoff == FQ_CUTOFF_SSM (-2): K = the tissue rank that spatial_similarity (below) reads
+ *     from the leading M = min(n_t, 64) spatial modes (K <= M/2).
  *  S_f = S - (S V_K) V_K^H (explicit subtraction);  pd[v] = (1/N_t) sum_f |S_f[v][f]|^2.
  *  iq       complex64 [n_t][n_vox];  gram complex128 [n_t][n_t] from casorati_gram;
  *  iq_filt  complex64 [n_t][n_vox] or NULL;  pd float32 [n_vox] or NULL;
@@ -171,6 +175,7 @@ int casorati_gram(const float* iq, int64_t n_vox, int32_t n_t, int32_t gram_mode
  *  K is limited to 64 (FQ_E_INVALID for a larger fixed cutoff; the knee result is
  *  clamped to 64 and the status word set to FQ_E_NUMERIC).
  * ------------------------------------------------------------------------------- */
+/* svd_workspace_size covers every cutoff mode (the FQ_CUTOFF_SSM pass included). */
 size_t svd_workspace_size(int64_t n_vox, int32_t n_t);
 int svd_clutter_filter(const float* iq, int64_t n_vox, int32_t n_t, const double* gram,
                        int32_t cutoff, void* ws, size_t ws_bytes, float* iq_filt, float* pd,
@@ -181,6 +186,33 @@ int svd_clutter_filter(const float* iq, int64_t n_vox, int32_t n_t, const double
  * Same workspace and status word as above. */
 int hermitian_eig(const double* gram, int32_t n_t, void* ws, size_t ws_bytes, double* lam,
                   double* vecs, int32_t* status, void* stream);
+
+/* ---------------------------------------------------------------------------------
+ * spatial_similarity -- the spatial-similarity matrix (SSM) of the singular-value
+ * analyses of Section 3: correlation coefficients, over voxels, between the magnitudes of
+ * the spatial modes (left singular vectors) U_k = S V_k / sigma_k, and the tissue rank
+ * read from it.  The scale 1/sigma_k does not change a correlation, so |S V_k| is used.
+ *   C_jk = cov_v(|U_j|, |U_k|) / (std_v |U_j| std_v |U_k|), clipped to [-1, 1];
+ *          a mode whose magnitude does not vary over the voxels gets NaN.
+ *   Tissue rank (the paper marks it by eye at the end of the leading block of mutually
+ *   similar modes): mode k >= 1 joins the block while a_k > b_k,
+ *          a_k = mean_{i<k} C_ik,  b_k = mean_{k<j<M} C_kj;
+ *   K = the first k in [1, min(M-2, M/2)] that does not join (NaN does not join), else
+ *   max(1, M/2).
+ *  iq       complex64 [n_t][n_vox];
+ *  vecs     complex128 [n_t][n_t], column k the k-th right singular vector (descending),
+ *           as hermitian_eig writes it; columns 0 .. n_modes-1 are read;
+ *  n_modes  M, 2 .. min(n_t, FQ_SSM_MAX_MODES);
+ *  ssm      float64 [n_modes][n_modes] (device);
+ *  k_tissue int32 [1] (device) or NULL.
+ *  |U| is formed with FP32 matrix-core products and never stored; the moments are
+ *  accumulated in FP64 and reduced in a fixed order (deterministic).
+ *  Errors: FQ_E_INVALID (sizes, pointers), FQ_E_WORKSPACE.
+ * ------------------------------------------------------------------------------- */
+size_t ssm_workspace_size(int64_t n_vox, int32_t n_t);
+int spatial_similarity(const float* iq, int64_t n_vox, int32_t n_t, const double* vecs,
+                       int32_t n_modes, void* ws, size_t ws_bytes, double* ssm,
+                       int32_t* k_tissue, void* stream);
 
 /* ---------------------------------------------------------------------------------
  * power_doppler -- pd[v] = (1/n_t) sum_f |iq[f][v]|^2 (Section 2.4.2 power Doppler map).

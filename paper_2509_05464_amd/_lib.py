@@ -19,6 +19,8 @@ LIB_PATH = os.path.join(HERE, 'libfqpd.so')
 
 FQ_MAX_ANGLES = 32
 FQ_MAX_NT = 512
+FQ_SSM_MAX_MODES = 64
+CUTOFF_KNEE, CUTOFF_SSM = -1, -2
 LCF_N_PARAM = 19170
 FQ_OK, FQ_E_INVALID, FQ_E_WORKSPACE, FQ_E_HIP, FQ_E_NUMERIC = range(5)
 INTERP_LINEAR, INTERP_HERMITE = 0, 1
@@ -91,6 +93,8 @@ _SIGS = {
     'svd_clutter_filter': (ctypes.c_int, [_vp, _i64, _i32, _vp, _i32, _vp, _sz, _vp, _vp, _vp, _vp, _vp, _vp]),
     'hermitian_eig': (ctypes.c_int, [_vp, _i32, _vp, _sz, _vp, _vp, _vp, _vp]),
     'power_doppler': (ctypes.c_int, [_vp, _i64, _i32, _vp, _vp]),
+    'ssm_workspace_size': (_sz, [_i64, _i32]),
+    'spatial_similarity': (ctypes.c_int, [_vp, _i64, _i32, _vp, _i32, _vp, _sz, _vp, _vp, _vp]),
     'lcf_act_size': (_sz, [_i64, _i32]),
     'lcf_forward': (ctypes.c_int, [_vp, _vp, _vp, _i64, _i32, _f32, _vp, _vp, _vp, _vp]),
     'lcf_backward': (ctypes.c_int, [_vp, _vp, _vp, _vp, _i64, _i32, _f32, _vp, _vp, _vp, _vp]),
@@ -219,6 +223,19 @@ def power_doppler(iq: torch.Tensor, pd: torch.Tensor) -> None:
     nt, nv = iq.shape
     st = lib().power_doppler(_ptr(_f32view(iq)), nv, nt, _ptr(pd), _stream())
     _check('power_doppler', st)
+
+
+def ssm_workspace_size(n_vox: int, n_t: int) -> int:
+    return lib().ssm_workspace_size(n_vox, n_t)
+
+
+def spatial_similarity(iq: torch.Tensor, vecs: torch.Tensor, n_modes: int, ws: torch.Tensor, ssm: torch.Tensor,
+                       k_tissue: Optional[torch.Tensor] = None) -> None:
+    """iq complex64 [Nt][Nv], vecs complex128 [Nt][Nt] -> ssm float64 [M][M], k_tissue int32 [1]."""
+    nt, nv = iq.shape
+    st = lib().spatial_similarity(_ptr(_f32view(iq)), nv, nt, _ptr(_f32view(vecs)), n_modes, _ptr(ws),
+                                  ws.numel() * ws.element_size(), _ptr(ssm), _ptr(k_tissue), _stream())
+    _check('spatial_similarity', st)
 
 
 # ----------------------------------------------------------------------------- learned filter

@@ -18,6 +18,13 @@ namespace fq {
 void set_error(const char* fmt, ...);
 int zero_async(void* p, size_t n_bytes, hipStream_t s);
 
+// ------------------------------------------------------------------ spatial similarity
+// Workspace bytes and launch of the SSM pass (ssm.hip); C == nullptr keeps the matrix in
+// the workspace, k_out == nullptr skips the rank rule.
+size_t ssm_bytes(int64_t n_vox, int n_t);
+int launch_ssm(const float* iq, int64_t n_vox, int n_t, const double* vecs, int n_modes, char* ws, double* C,
+               int* k_out, hipStream_t s);
+
 #define FQ_REQUIRE(cond, ...)                         \
     do {                                              \
         if (!(cond)) {                                \

@@ -422,6 +422,8 @@ __global__ void rank_kernel(const RankArgs a) {
         int K;
         if (a.cutoff >= 0) {
             K = a.cutoff;
+        } else if (a.cutoff == FQ_CUTOFF_SSM) {
+            K = *a.k_used;   // written by the spatial-similarity pass
         } else if (n < 4 || !(a.lam[0] > 0.0)) {
             K = 1;
         } else {
@@ -608,9 +610,8 @@ PdFn pd_fn(int k) {
 using namespace fq;
 
 extern "C" size_t svd_workspace_size(int64_t n_vox, int32_t n_t) {
-    (void)n_vox;
-    if (n_t < 1) return 0;
-    return svd_layout(n_t).total;
+    if (n_t < 1 || n_vox < 1) return 0;
+    return svd_layout(n_t).total + ssm_bytes(n_vox, n_t);
 }
 
 extern "C" int hermitian_eig(const double* gram, int32_t n_t, void* ws, size_t ws_bytes, double* lam, double* vecs,
@@ -630,14 +631,16 @@ extern "C" int svd_clutter_filter(const float* iq, int64_t n_vox, int32_t n_t, c
                                   int32_t* k_used, int32_t* status, void* stream) {
     FQ_REQUIRE(n_t >= 1 && n_t <= FQ_MAX_NT, "n_t must be 1..%d", FQ_MAX_NT);
     FQ_REQUIRE(n_vox >= 1, "n_vox must be >= 1");
-    FQ_REQUIRE(cutoff >= -1 && cutoff <= n_t, "cutoff must be -1 (knee) or 0..n_t");
+    FQ_REQUIRE(cutoff >= FQ_CUTOFF_SSM && cutoff <= n_t, "cutoff must be -2 (SSM), -1 (knee) or 0..n_t");
+    FQ_REQUIRE(cutoff != FQ_CUTOFF_SSM || n_t >= 2, "the SSM cutoff needs n_t >= 2");
     FQ_REQUIRE(cutoff <= KMAX, "fixed cutoff above %d is not supported", KMAX);
     FQ_REQUIRE(iq && gram && ws && sigma && k_used && aligned16(iq) && aligned16(gram) && aligned16(ws),
                "null or misaligned pointer");
     FQ_REQUIRE(!iq_filt || aligned16(iq_filt), "misaligned iq_filt");
     const SvdWs L = svd_layout(n_t);
-    if (ws_bytes < L.total) {
-        set_error("workspace too small: %zu < %zu bytes", ws_bytes, L.total);
+    const size_t need = L.total + (cutoff == FQ_CUTOFF_SSM ? ssm_bytes(n_vox, n_t) : 0);
+    if (ws_bytes < need) {
+        set_error("workspace too small: %zu < %zu bytes", ws_bytes, need);
         return FQ_E_WORKSPACE;
     }
     hipStream_t s = as_stream(stream);
@@ -646,6 +649,11 @@ extern "C" int svd_clutter_filter(const float* iq, int64_t n_vox, int32_t n_t, c
     double* vecs = reinterpret_cast<double*>(w + L.off_vecs);
     int st = launch_eig(gram, n_t, w, L, lam, sigma, vecs, std::min(n_t, KMAX), status, s);
     if (st != FQ_OK) return st;
+    if (cutoff == FQ_CUTOFF_SSM) {
+        // the leading min(n_t, 64) eigenvectors are the ones back-transformed above
+        st = launch_ssm(iq, n_vox, n_t, vecs, std::min(n_t, FQ_SSM_MAX_MODES), w + L.total, nullptr, k_used, s);
+        if (st != FQ_OK) return st;
+    }
     RankArgs ra{lam, reinterpret_cast<const double2*>(vecs), reinterpret_cast<float2*>(w + L.off_vk), k_used, status,
                 n_t, cutoff};
     hipLaunchKernelGGL(rank_kernel, dim3(1), dim3(256), 0, s, ra);

@@ -70,3 +70,27 @@ def gpu_svd_pd(iq, cutoff, mode=0):
     iqf = torch.empty_like(iq)
     fq.svd_clutter_filter(iq, G, sws, sigma, k, cutoff, iq_filt=iqf, pd=pd, status=status)
     return dict(G=G, sigma=sigma, k=k, status=status, pd=pd, iq_filt=iqf)
+
+
+def designed_modes_casorati(nv, nt, k_tissue, seed, n_blood=6):
+    """Casorati matrix S = U0 diag(s) V^H (returned frame-major, complex64 [nt][nv]) with
+    designed spatial magnitudes |U0|: k_tissue modes share one smooth footprint over the
+    whole volume, n_blood modes share a localised vessel footprint, the rest are
+    independent speckle; V (complex128 [nt][nt]) is a seeded random unitary matrix and
+    s spans 60 dB.  S V = U0 diag(s), so the SSM of S and V is the correlation matrix of
+    the designed magnitudes and its tissue rank is k_tissue."""
+    rng = np.random.default_rng(seed)
+    x = np.arange(nv) / nv
+    tissue = 1.0 + 0.5 * np.sin(2 * np.pi * 7 * x)
+    vessel = np.where((x > 0.25) & (x < 0.35), 1.0, 0.05)
+    mag = np.abs(rng.standard_normal((nv, nt)))
+    for k in range(k_tissue):
+        mag[:, k] = np.abs(tissue * (1 + 0.1 * rng.standard_normal(nv)))
+    for k in range(k_tissue, min(nt, k_tissue + n_blood)):
+        mag[:, k] = np.abs(vessel * (1 + 0.1 * rng.standard_normal(nv)))
+    U0 = mag * np.exp(2j * np.pi * rng.random((nv, nt)))
+    q, r = np.linalg.qr(rng.standard_normal((nt, nt)) + 1j * rng.standard_normal((nt, nt)))
+    V = q * (np.diag(r) / np.abs(np.diag(r)))
+    s = np.geomspace(1e3, 1.0, nt)
+    S = (U0 * s) @ V.conj().T
+    return np.ascontiguousarray(S.T).astype(np.complex64), V

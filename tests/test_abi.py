@@ -55,6 +55,12 @@ def test_workspace_queries_without_gpu(lib):
     assert full == blk * 25 and blk == acq.n_angles * acq.n_elem * acq.n_samples * 8 * 8
     assert fq.gram_workspace_size(acq.n_vox, acq.n_frames, 0) > 0
     assert fq.svd_workspace_size(acq.n_vox, acq.n_frames) > 0
+    # the SSM pass: 512 workgroup partials of a 64 x 64 Gram plus 64 column sums at most,
+    # and the filter's workspace covers it
+    ssm = fq.ssm_workspace_size(acq.n_vox, acq.n_frames)
+    assert 512 * (64 * 64 + 64) * 8 <= ssm < 512 * (64 * 64 + 64) * 8 + (1 << 20)
+    assert fq.ssm_workspace_size(100, 20) < ssm
+    assert fq.svd_workspace_size(acq.n_vox, acq.n_frames) > ssm
     assert fq.lcf_act_size(4096, 200) > 4096 * 200 * 194 * 2
 
 
@@ -69,3 +75,13 @@ def test_invalid_arguments_return_status(lib):
     assert st == 1
     st = L.svd_clutter_filter(None, 10, 600, None, 2, None, 0, None, None, None, None, None, None)
     assert st == 1 and b'n_t' in L.fq_last_error()
+    st = L.svd_clutter_filter(None, 10, 20, None, -3, None, 0, None, None, None, None, None, None)
+    assert st == 1 and b'cutoff' in L.fq_last_error()
+    st = L.spatial_similarity(None, 10, 20, None, 1, None, 0, None, None, None)
+    assert st == 1 and b'n_modes' in L.fq_last_error()
+    st = L.spatial_similarity(None, 10, 20, None, 21, None, 0, None, None, None)
+    assert st == 1 and b'n_modes' in L.fq_last_error()
+    st = L.spatial_similarity(None, 10, 100, None, 65, None, 0, None, None, None)
+    assert st == 1 and b'n_modes' in L.fq_last_error()
+    st = L.spatial_similarity(None, 10, 20, None, 4, None, 0, None, None, None)
+    assert st == 1 and b'null' in L.fq_last_error()
