@@ -28,6 +28,7 @@ if ROOT not in sys.path:
 
 PEAK_FP32_FMA_TFLOPS = 78.6      # 256 CU x 4 SIMD x 16 lanes x 2 FLOP x 2.4 GHz, FP32 FMA without packed math
 PEAK_FP32_PACKED_TFLOPS = 157.3  # published FP32 vector peak (needs packed FP32 instructions)
+PEAK_FP32_MFMA_TFLOPS = 157.3    # published dense FP32 matrix-core peak
 DAS_FLOP_PER_UNIT = 16           # two complex multiply-adds per voxel*element*angle*frame (linear)
 RF_FLOP_PER_TAP = 5              # per pulse sample: recurrence multiply + FMA, accumulate FMA
 
@@ -419,6 +420,51 @@ def main():
     dominant = 'rf_synth_kernel' if stage_ms_rf > stage_ms_das else 'das_kernel'
     out['roofline'] = dict(out['rooflines'][dominant], kernel=dominant)
 
+    # spatial-similarity matrix of the leading modes and the clutter filter with the SSM
+    # cutoff, on the step's IQ and FP32 Gram (outside the step: the workload's cutoff is
+    # the knee)
+    _log('[bench] spatial similarity')
+    M = min(F, fq.FQ_SSM_MAX_MODES)
+    lam_e = torch.empty(F, dtype=torch.float64, device=dev)
+    vecs = torch.empty((F, F), dtype=torch.complex128, device=dev)
+    st3 = torch.zeros(1, dtype=torch.int32, device=dev)
+    fq.hermitian_eig(G, sws, lam_e, vecs, st3)
+    ssm_ws = torch.empty(fq.ssm_workspace_size(NV, F), dtype=torch.uint8, device=dev)
+    C_ssm = torch.empty((M, M), dtype=torch.float64, device=dev)
+    k_ssm = torch.zeros(1, dtype=torch.int32, device=dev)
+    k3 = torch.zeros(1, dtype=torch.int32, device=dev)
+    pd_ssm = torch.empty(NV, dtype=torch.float32, device=dev)
+    sigma3 = torch.empty_like(sigma)
+
+    def timed(fn, reps=5):
+        fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+    ssm_ms = timed(lambda: fq.spatial_similarity(iq, vecs, M, ssm_ws, C_ssm, k_ssm))
+    svd_ssm_ms = timed(lambda: fq.svd_clutter_filter(iq, G, sws, sigma3, k3, fq.CUTOFF_SSM, pd=pd_ssm, status=st3))
+    # MFMA work of one SSM pass: U = S V over the 64-mode tile (8 FLOP per complex
+    # multiply-add) and the 64 x 64 Gram of |U| (2 FLOP per multiply-add)
+    ssm_flop = 8.0 * NV * F * fq.FQ_SSM_MAX_MODES + 2.0 * NV * fq.FQ_SSM_MAX_MODES ** 2
+    out['ssm'] = {
+        'n_modes': M,
+        'k_tissue': int(k_ssm.item()),
+        'k_used_by_filter': int(k3.item()),
+        'ms': ssm_ms,
+        'achieved': ssm_flop / (ssm_ms / 1e3) / 1e12,
+        'peak': PEAK_FP32_MFMA_TFLOPS,
+        'unit': 'TFLOP/s',
+        'frac': ssm_flop / (ssm_ms / 1e3) / 1e12 / PEAK_FP32_MFMA_TFLOPS,
+        'svd_filter_with_ssm_cutoff_ms': svd_ssm_ms,
+        'eig_status': int(st3.item()),
+    }
+
     if not args.no_truth:
         # untimed: ground-truth blood PD (DAS of blood-only RF) and each path's error
         _log('[bench] ground-truth pass')
@@ -444,6 +490,7 @@ def main():
             return float((torch.linalg.norm(p.double() - pd_svd.double()) / torch.linalg.norm(pd_svd.double())).item())
 
         out['pd_error_db_vs_blood_truth'] = {'svd_fp32': err_db(pd_svd), 'svd_split4_bf16': err_db(pd_split),
+                                             'svd_fp32_ssm_cutoff': err_db(pd_ssm),
                                              'svd_split3_bf16_at_fp32_k': err_db(pd_split3),
                                              'learned': err_db(pd_lcf), 'learned_with_fallback': err_db(pd_out)}
         out['pd_rel_l2_vs_fp32_svd'] = {'svd_split4_bf16': rel(pd_split), 'svd_split3_bf16_at_fp32_k': rel(pd_split3)}
