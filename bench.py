@@ -465,6 +465,24 @@ def main():
         'eig_status': int(st3.item()),
     }
 
+    # display: the PD volume over 60 dB and its three maximum-intensity projections
+    disp_ws = torch.empty(fq.display_workspace_size(NV), dtype=torch.uint8, device=dev)
+    pd_db = torch.empty((acq.nz, acq.ny, acq.nx), dtype=torch.float32, device=dev)
+    mips = [torch.empty(shp, dtype=torch.float32, device=dev)
+            for shp in ((acq.ny, acq.nx), (acq.nz, acq.nx), (acq.nz, acq.ny))]
+
+    def show():
+        fq.display_db(pd_svd.view(acq.nz, acq.ny, acq.nx), 60.0, disp_ws, pd_db)
+        for plane, m in zip((fq.MIP_XY, fq.MIP_XZ, fq.MIP_YZ), mips):
+            fq.mip(pd_db, plane, m)
+
+    disp_ms = timed(show, reps=20)
+    # algorithmic bytes: PD read twice (reference, then dB) and dB written, then three reads
+    # of the dB volume for the projections
+    disp_bytes = 4.0 * NV * (2 + 1 + 3)
+    out['display'] = {'ms': disp_ms, 'gb_per_s': disp_bytes / (disp_ms / 1e3) / 1e9,
+                      'what': 'PD volume over 60 dB + MIPs onto x-y, x-z, y-z'}
+
     if not args.no_truth:
         # untimed: ground-truth blood PD (DAS of blood-only RF) and each path's error
         _log('[bench] ground-truth pass')

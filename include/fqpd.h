@@ -48,6 +48,8 @@ enum { FQ_OK = 0, FQ_E_INVALID = 1, FQ_E_WORKSPACE = 2, FQ_E_HIP = 3, FQ_E_NUMER
 enum { FQ_INTERP_LINEAR = 0, FQ_INTERP_HERMITE = 1 };
 enum { FQ_GRAM_FP32 = 0, FQ_GRAM_SPLIT_BF16 = 1, FQ_GRAM_BF16 = 2, FQ_GRAM_SPLIT4_BF16 = 3 };
 enum { FQ_CUTOFF_KNEE = -1, FQ_CUTOFF_SSM = -2 };
+enum { FQ_DISP_POWER = 0, FQ_DISP_IQ = 1 };
+enum { FQ_MIP_XY = 0, FQ_MIP_XZ = 1, FQ_MIP_YZ = 2 };
 
 typedef struct {
     int32_t nx_el, ny_el;     /* regular matrix array, nx_el*ny_el elements */
@@ -219,6 +221,27 @@ int spatial_similarity(const float* iq, int64_t n_vox, int32_t n_t, const double
  *  iq complex64 [n_t][n_vox]; pd float32 [n_vox].
  * ------------------------------------------------------------------------------- */
 int power_doppler(const float* iq, int64_t n_vox, int32_t n_t, float* pd, void* stream);
+
+/* ---------------------------------------------------------------------------------
+ * display_db -- log compression over a dynamic range (Section 2.4.2: B-mode and uPDI
+ * volumes are log-compressed and shown over a dynamic range; the results use 75 dB for
+ * B-mode and 60 dB for power Doppler).
+ *   p   = in[i] (kind FQ_DISP_POWER: float32 power values such as PD, >= 0) or
+ *         |in[i]|^2 (kind FQ_DISP_IQ: complex64 IQ, so that 10 log10 p = 20 log10 |IQ|);
+ *   out[i] = max(-dr_db, 10 log10(p / max_j p_j)) (float32 [n]); an all-zero input, and
+ *         zero entries, are shown at -dr_db.  NaN inputs are not supported.
+ *  ws     workspace of display_workspace_size(n) bytes (block maxima);
+ *  peak   float32 [1] (device) receives max_j p_j, or NULL.
+ * mip -- maximum-intensity projection of vol[iz][iy][ix] (x fastest, the voxel order of
+ *   fq_grid) onto a plane: FQ_MIP_XY -> out[ny][nx] (max over z), FQ_MIP_XZ -> out[nz][nx]
+ *   (max over y), FQ_MIP_YZ -> out[nz][ny] (max over x).  Exact (a maximum has no
+ *   rounding); apply it to PD or to display_db output alike (the logarithm is monotonic).
+ * ------------------------------------------------------------------------------- */
+size_t display_workspace_size(int64_t n);
+int display_db(const float* in, int64_t n, int32_t kind, float dr_db, void* ws, size_t ws_bytes,
+               float* out, float* peak, void* stream);
+int mip(const float* vol, int32_t nx, int32_t ny, int32_t nz, int32_t plane, float* out,
+        void* stream);
 
 /* ---------------------------------------------------------------------------------
  * Learned slow-time clutter filter.  Per voxel series s = iq[:, v]:

@@ -21,6 +21,8 @@ FQ_MAX_ANGLES = 32
 FQ_MAX_NT = 512
 FQ_SSM_MAX_MODES = 64
 CUTOFF_KNEE, CUTOFF_SSM = -1, -2
+DISP_POWER, DISP_IQ = 0, 1
+MIP_XY, MIP_XZ, MIP_YZ = 0, 1, 2
 LCF_N_PARAM = 19170
 FQ_OK, FQ_E_INVALID, FQ_E_WORKSPACE, FQ_E_HIP, FQ_E_NUMERIC = range(5)
 INTERP_LINEAR, INTERP_HERMITE = 0, 1
@@ -94,6 +96,9 @@ _SIGS = {
     'hermitian_eig': (ctypes.c_int, [_vp, _i32, _vp, _sz, _vp, _vp, _vp, _vp]),
     'power_doppler': (ctypes.c_int, [_vp, _i64, _i32, _vp, _vp]),
     'ssm_workspace_size': (_sz, [_i64, _i32]),
+    'display_workspace_size': (_sz, [_i64]),
+    'display_db': (ctypes.c_int, [_vp, _i64, _i32, _f32, _vp, _sz, _vp, _vp, _vp]),
+    'mip': (ctypes.c_int, [_vp, _i32, _i32, _i32, _i32, _vp, _vp]),
     'spatial_similarity': (ctypes.c_int, [_vp, _i64, _i32, _vp, _i32, _vp, _sz, _vp, _vp, _vp]),
     'lcf_act_size': (_sz, [_i64, _i32]),
     'lcf_forward': (ctypes.c_int, [_vp, _vp, _vp, _i64, _i32, _f32, _vp, _vp, _vp, _vp]),
@@ -236,6 +241,26 @@ def spatial_similarity(iq: torch.Tensor, vecs: torch.Tensor, n_modes: int, ws: t
     st = lib().spatial_similarity(_ptr(_f32view(iq)), nv, nt, _ptr(_f32view(vecs)), n_modes, _ptr(ws),
                                   ws.numel() * ws.element_size(), _ptr(ssm), _ptr(k_tissue), _stream())
     _check('spatial_similarity', st)
+
+
+def display_workspace_size(n: int) -> int:
+    return lib().display_workspace_size(n)
+
+
+def display_db(x: torch.Tensor, dr_db: float, ws: torch.Tensor, out: torch.Tensor,
+               peak: Optional[torch.Tensor] = None) -> None:
+    """x float32 power values or complex64 IQ (any shape, contiguous) -> out float32 dB, same shape."""
+    kind = DISP_IQ if x.is_complex() else DISP_POWER
+    st = lib().display_db(_ptr(_f32view(x)), x.numel(), kind, dr_db, _ptr(ws), ws.numel() * ws.element_size(),
+                          _ptr(out), _ptr(peak), _stream())
+    _check('display_db', st)
+
+
+def mip(vol: torch.Tensor, plane: int, out: torch.Tensor) -> None:
+    """vol float32 [nz][ny][nx] -> out: MIP_XY [ny][nx], MIP_XZ [nz][nx], MIP_YZ [nz][ny]."""
+    nz, ny, nx = vol.shape
+    st = lib().mip(_ptr(vol), nx, ny, nz, plane, _ptr(out), _stream())
+    _check('mip', st)
 
 
 # ----------------------------------------------------------------------------- learned filter
