@@ -98,11 +98,14 @@ class SceneSpec:
     vessels: str                     # 'one_45deg' | 'random3' | 'murray31' | 'none'
     vessel_diam: float = 1e-3        # 'one_45deg': lumen diameter, m
     vmax: float = 20e-3              # 'one_45deg': centre-line speed, m/s
-    motion: str = 'static'           # 'static' | 'cardiac_resp'
+    motion: str = 'static'           # 'static' | 'cardiac_resp' | 'velocity' | 'rotation'
     z_lo: Optional[float] = None     # scene depth range; default grid depth +- margin
     z_hi: Optional[float] = None
     margin: float = 1e-3             # lateral (and default depth) margin around the grid
     seed: int = 0
+    velocity: Tuple[float, float, float] = (0.0, 0.0, 0.0)   # 'velocity': m/s
+    rot_omega: float = 0.0           # 'rotation': rad/s about -y (angular velocity (0, -w, 0))
+    rot_centre: Tuple[float, float, float] = (0.0, 0.0, 0.025)   # 'rotation': m
 
 
 @dataclasses.dataclass(frozen=True)
@@ -168,6 +171,31 @@ CONFIGS['c4_small'] = Config('c4_small', _acq(16, 16, _T3X, 32, 32, 32, 64, 1000
 
 def get_config(name: str) -> Config:
     return CONFIGS[name]
+
+
+# Tissue-motion sweep (the synthetic analog of the motion study of Section 3): steady
+# axial motion V_z = 2, 4, 8 mm/s; lateral V_x = 2, 4, 8 mm/s at V_z = 4 mm/s; rotation
+# V = (0, -w, 0) x (r - (0, 0, 2.5 cm)) with w = 1 rad/s scaled by 0.1, 0.2, 0.4.  Vessels
+# move with the tissue.  Geometry of the training workload (64^3, 9 transmits, 200 frames).
+MOTION_SWEEP = (
+    ('vz2', dict(motion='velocity', velocity=(0.0, 0.0, 2e-3))),
+    ('vz4', dict(motion='velocity', velocity=(0.0, 0.0, 4e-3))),
+    ('vz8', dict(motion='velocity', velocity=(0.0, 0.0, 8e-3))),
+    ('vx2_vz4', dict(motion='velocity', velocity=(2e-3, 0.0, 4e-3))),
+    ('vx4_vz4', dict(motion='velocity', velocity=(4e-3, 0.0, 4e-3))),
+    ('vx8_vz4', dict(motion='velocity', velocity=(8e-3, 0.0, 4e-3))),
+    ('rot0.1', dict(motion='rotation', rot_omega=0.1)),
+    ('rot0.2', dict(motion='rotation', rot_omega=0.2)),
+    ('rot0.4', dict(motion='rotation', rot_omega=0.4)),
+)
+
+
+def motion_sweep_configs(base: str = 'c4_train', seed: int = 3000) -> dict:
+    """name -> Config of the motion sweep, one seeded scene recipe for every case."""
+    b = CONFIGS[base]
+    return {name: dataclasses.replace(b, name=f'sweep_{name}',
+                                      scene=dataclasses.replace(b.scene, seed=seed, **kw))
+            for name, kw in MOTION_SWEEP}
 
 
 def scaled(cfg: Config, *, frames: Optional[int] = None, seed: Optional[int] = None,

@@ -49,6 +49,37 @@ class Scene:
         return self.tissue_pos.shape[0] == 1
 
 
+def rigid_motion(spec, t: np.ndarray):
+    """Closed-form solution of the trajectory integral (Section 2.2.2) for the tissue
+    velocity fields: p(t) = c + R(t) (p0 - c) + d(t).  Returns R [F][3][3], d [F][3],
+    c [3].  'velocity': d = V t.  'rotation': V(r) = W x (r - c) with W = (0, -w, 0), whose
+    solution rotates about the -y axis through c by the angle w t."""
+    t = np.asarray(t, dtype=np.float64)
+    R = np.broadcast_to(np.eye(3), (t.size, 3, 3)).copy()
+    d = np.zeros((t.size, 3))
+    c = np.zeros(3)
+    if spec.motion == 'velocity':
+        d = t[:, None] * np.asarray(spec.velocity, dtype=np.float64)[None, :]
+    elif spec.motion == 'rotation':
+        c = np.asarray(spec.rot_centre, dtype=np.float64)
+        a = spec.rot_omega * t
+        ca, sa = np.cos(a), np.sin(a)
+        R[:, 0, 0] = ca
+        R[:, 0, 2] = -sa
+        R[:, 2, 0] = sa
+        R[:, 2, 2] = ca
+    else:
+        d = tissue_displacement(spec.motion, t)
+    return R, d, c
+
+
+def _apply_motion(p: np.ndarray, R: np.ndarray, d: np.ndarray, c: np.ndarray, motion: str) -> np.ndarray:
+    """Positions at every frame: p [F][n][3] (tissue-frame positions per frame) or [1][n][3]."""
+    if motion != 'rotation':
+        return p + d[:, None, :]
+    return c[None, None, :] + np.einsum('fij,fnj->fni', R, p - c[None, None, :]) + d[:, None, :]
+
+
 def tissue_displacement(motion: str, t: np.ndarray) -> np.ndarray:
     """Rigid tissue displacement d(t), shape [len(t)][3] (metres)."""
     t = np.asarray(t, dtype=np.float64)
@@ -61,6 +92,8 @@ def tissue_displacement(motion: str, t: np.ndarray) -> np.ndarray:
         d[:, 0] = resp
         d[:, 2] = card + resp
         return d
+    if motion in ('velocity', 'rotation'):
+        raise ValueError(f'motion {motion!r} is given by rigid_motion (it needs the scene spec)')
     raise ValueError(f'unknown motion {motion!r}')
 
 
@@ -182,7 +215,7 @@ def make_scene(cfg: Config, seed: Optional[int] = None) -> Scene:
     vessels = _make_vessels(cfg, rng)
     F = a.n_frames
     times = np.arange(F, dtype=np.float64) / a.prf
-    disp = tissue_displacement(s.motion, times)                     # [F][3]
+    Rm, disp, cm = rigid_motion(s, times)                           # [F][3][3], [F][3], [3]
 
     # ---- blood: split by lumen volume, uniform in each lumen
     nb = s.n_blood if vessels else 0
@@ -210,8 +243,8 @@ def make_scene(cfg: Config, seed: Optional[int] = None) -> Scene:
         L = 2 * v.half_len
         sf = s0[None, :] + speed[None, :] * times[:, None]           # [F][n]
         sf = (sf + v.half_len) % L - v.half_len
-        bpos[:, k:k + n, :] = (v.centre[None, None, :] + sf[:, :, None] * v.axis[None, None, :]
-                               + radial[None, :, :] + disp[:, None, :])
+        bpos[:, k:k + n, :] = _apply_motion(v.centre[None, None, :] + sf[:, :, None] * v.axis[None, None, :]
+                                            + radial[None, :, :], Rm, disp, cm, s.motion)
         bves[k:k + n] = iv
         brad[k:k + n] = rr / v.radius
         k += n
@@ -229,7 +262,7 @@ def make_scene(cfg: Config, seed: Optional[int] = None) -> Scene:
     if s.motion == 'static':
         tpos = tp[None, :, :]
     else:
-        tpos = tp[None, :, :] + disp[:, None, :]
+        tpos = _apply_motion(np.broadcast_to(tp[None, :, :], (F,) + tp.shape), Rm, disp, cm, s.motion)
     return Scene(tissue_pos=np.ascontiguousarray(tpos, dtype=np.float32),
                  tissue_amp=tamp.astype(np.float32),
                  blood_pos=np.ascontiguousarray(bpos, dtype=np.float32),

@@ -89,3 +89,63 @@ def test_ssm_rank_minimises_blood_pd_error_on_small_scene(orc):
     errs = [err_db(K) for K in range(7)]
     assert out['K'] == int(np.argmin(errs))
     assert errs[out['K']] < -6.0
+
+
+def _rk4(vel, r0, t1, steps=2000):
+    r = np.array(r0, dtype=np.float64)
+    h = t1 / steps
+    for _ in range(steps):
+        k1 = vel(r)
+        k2 = vel(r + 0.5 * h * k1)
+        k3 = vel(r + 0.5 * h * k2)
+        k4 = vel(r + h * k3)
+        r = r + h / 6 * (k1 + 2 * k2 + 2 * k3 + k4)
+    return r
+
+
+def test_rotation_motion_solves_the_trajectory_integral():
+    """Section 2.2.2: a scatterer's position is the integral of the velocity field along
+    its path.  For V(r) = (0, -w, 0) x (r - c) the closed form of the generator must match
+    a fourth-order Runge-Kutta integration of that field (to 1e-12 m)."""
+    from fqscene import motion_sweep_configs, rigid_motion
+    spec = motion_sweep_configs()['rot0.4'].scene
+    W = np.array([0.0, -spec.rot_omega, 0.0])
+    c = np.asarray(spec.rot_centre)
+    t = np.array([0.0, 0.05, 0.199])
+    R, d, cc = rigid_motion(spec, t)
+    rng = np.random.default_rng(3)
+    for p0 in rng.uniform(-5e-3, 15e-3, size=(4, 3)):
+        for i, ti in enumerate(t):
+            want = _rk4(lambda r: np.cross(W, r - c), p0, ti) if ti > 0 else p0
+            got = cc + R[i] @ (p0 - cc) + d[i]
+            np.testing.assert_allclose(got, want, atol=1e-12)
+    # the velocity at t = 0 is the field itself: (-w (z - z_c), 0, w x)
+    p0 = np.array([1e-3, 2e-3, 10e-3])
+    R2, _, _ = rigid_motion(spec, np.array([0.0, 1e-6]))
+    v = (R2[1] - R2[0]) @ (p0 - c) / 1e-6
+    np.testing.assert_allclose(v, [-spec.rot_omega * (p0[2] - c[2]), 0.0, spec.rot_omega * p0[0]], rtol=1e-5)
+
+
+@pytest.mark.parametrize('case', ['vx8_vz4', 'rot0.4'])
+def test_sweep_scenes_move_rigidly_with_their_vessels(case):
+    """Tissue follows the rigid motion exactly; blood stays inside the moved lumina and
+    tissue outside them."""
+    from fqscene import motion_sweep_configs, rigid_motion
+    from fqscene.configs import scaled as sc_scaled
+    from fqscene.scene import _inside_any
+    cfg = sc_scaled(motion_sweep_configs()[case], frames=5)
+    sc = make_scene(cfg)
+    R, d, c = rigid_motion(cfg.scene, sc.times)
+    p0 = sc.tissue_pos[0].astype(np.float64)
+    def back(p, f):                                          # inverse rigid motion (R orthogonal)
+        return (p.astype(np.float64) - c - d[f]) @ R[f] + c
+
+    for f in range(5):
+        tis = back(sc.tissue_pos[f], f)
+        np.testing.assert_allclose(tis, back(sc.tissue_pos[0], 0), atol=2e-9)
+        assert _inside_any(back(sc.blood_pos[f], f), sc.vessels).mean() > 0.999
+        assert _inside_any(tis, sc.vessels).mean() < 1e-3
+    if case.startswith('v'):
+        v = np.asarray(cfg.scene.velocity)
+        np.testing.assert_allclose(sc.tissue_pos[4].astype(np.float64) - p0, np.broadcast_to(v * sc.times[4], p0.shape),
+                                   atol=2e-9)
