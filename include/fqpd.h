@@ -48,7 +48,7 @@ enum { FQ_OK = 0, FQ_E_INVALID = 1, FQ_E_WORKSPACE = 2, FQ_E_HIP = 3, FQ_E_NUMER
 enum { FQ_INTERP_LINEAR = 0, FQ_INTERP_HERMITE = 1 };
 enum { FQ_GRAM_FP32 = 0, FQ_GRAM_SPLIT_BF16 = 1, FQ_GRAM_BF16 = 2, FQ_GRAM_SPLIT4_BF16 = 3 };
 enum { FQ_CUTOFF_KNEE = -1, FQ_CUTOFF_SSM = -2 };
-enum { FQ_DISP_POWER = 0, FQ_DISP_IQ = 1 };
+enum { FQ_DISP_POWER = 0, FQ_DISP_IQ = 1, FQ_DISP_UNIT = 2 };
 enum { FQ_MIP_XY = 0, FQ_MIP_XZ = 1, FQ_MIP_YZ = 2 };
 
 typedef struct {
@@ -230,6 +230,8 @@ int power_doppler(const float* iq, int64_t n_vox, int32_t n_t, float* pd, void* 
  *         |in[i]|^2 (kind FQ_DISP_IQ: complex64 IQ, so that 10 log10 p = 20 log10 |IQ|);
  *   out[i] = max(-dr_db, 10 log10(p / max_j p_j)) (float32 [n]); an all-zero input, and
  *         zero entries, are shown at -dr_db.  NaN inputs are not supported.
+ *   kind | FQ_DISP_UNIT gives grey levels instead: out[i] = 1 + (the dB value) / dr_db,
+ *         in [0, 1] (the floor at 0, the peak at 1).
  *  ws     workspace of display_workspace_size(n) bytes (block maxima);
  *  peak   float32 [1] (device) receives max_j p_j, or NULL.
  * mip -- maximum-intensity projection of vol[iz][iy][ix] (x fastest, the voxel order of
@@ -242,6 +244,18 @@ int display_db(const float* in, int64_t n, int32_t kind, float dr_db, void* ws, 
                float* out, float* peak, void* stream);
 int mip(const float* vol, int32_t nx, int32_t ny, int32_t nz, int32_t plane, float* out,
         void* stream);
+
+/* ---------------------------------------------------------------------------------
+ * image_quality -- MSE, PSNR and SSIM of img against ref (Section 2.4.3; applied to the
+ * maximum-intensity projections), both float32 [ny][nx] (device), nx, ny >= 11.
+ *   MSE = mean (img - ref)^2;  PSNR = 10 log10(data_range^2 / MSE) (+inf when MSE = 0);
+ *   SSIM (Wang et al., IEEE TIP 2004): 11 x 11 Gaussian window, sigma 1.5, weights summing
+ *   to 1, K1 = 0.01, K2 = 0.03 (C = (K data_range)^2), window-weighted moments, mean over
+ *   the positions where the window lies inside the image.
+ *  out float64 [3] (device): MSE, PSNR, SSIM.  FP64 throughout, fixed reduction order.
+ * ------------------------------------------------------------------------------- */
+int image_quality(const float* img, const float* ref, int32_t nx, int32_t ny, double data_range,
+                  double* out, void* stream);
 
 /* ---------------------------------------------------------------------------------
  * Learned slow-time clutter filter.  Per voxel series s = iq[:, v]:

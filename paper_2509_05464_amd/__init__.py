@@ -12,7 +12,7 @@ from ._lib import (  # noqa: F401
     Probe, Tx, Grid, Pulse, make_probe, make_tx, make_grid, make_pulse, lib,
     rf_synth, das_workspace_size, das_beamform, das_demodulate, das_delay_sum, gram_workspace_size, casorati_gram,
     svd_workspace_size, svd_clutter_filter, hermitian_eig, power_doppler, ssm_workspace_size, spatial_similarity,
-    display_workspace_size, display_db, mip,
+    display_workspace_size, display_db, mip, image_quality,
     lcf_act_size, lcf_forward, lcf_backward, lcf_adam_step, lcf_gather,
     fallback_workspace_size, lcf_fallback,
 )

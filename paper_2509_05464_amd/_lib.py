@@ -21,7 +21,7 @@ FQ_MAX_ANGLES = 32
 FQ_MAX_NT = 512
 FQ_SSM_MAX_MODES = 64
 CUTOFF_KNEE, CUTOFF_SSM = -1, -2
-DISP_POWER, DISP_IQ = 0, 1
+DISP_POWER, DISP_IQ, DISP_UNIT = 0, 1, 2
 MIP_XY, MIP_XZ, MIP_YZ = 0, 1, 2
 LCF_N_PARAM = 19170
 FQ_OK, FQ_E_INVALID, FQ_E_WORKSPACE, FQ_E_HIP, FQ_E_NUMERIC = range(5)
@@ -99,6 +99,7 @@ _SIGS = {
     'display_workspace_size': (_sz, [_i64]),
     'display_db': (ctypes.c_int, [_vp, _i64, _i32, _f32, _vp, _sz, _vp, _vp, _vp]),
     'mip': (ctypes.c_int, [_vp, _i32, _i32, _i32, _i32, _vp, _vp]),
+    'image_quality': (ctypes.c_int, [_vp, _vp, _i32, _i32, ctypes.c_double, _vp, _vp]),
     'spatial_similarity': (ctypes.c_int, [_vp, _i64, _i32, _vp, _i32, _vp, _sz, _vp, _vp, _vp]),
     'lcf_act_size': (_sz, [_i64, _i32]),
     'lcf_forward': (ctypes.c_int, [_vp, _vp, _vp, _i64, _i32, _f32, _vp, _vp, _vp, _vp]),
@@ -248,9 +249,10 @@ def display_workspace_size(n: int) -> int:
 
 
 def display_db(x: torch.Tensor, dr_db: float, ws: torch.Tensor, out: torch.Tensor,
-               peak: Optional[torch.Tensor] = None) -> None:
-    """x float32 power values or complex64 IQ (any shape, contiguous) -> out float32 dB, same shape."""
-    kind = DISP_IQ if x.is_complex() else DISP_POWER
+               peak: Optional[torch.Tensor] = None, unit: bool = False) -> None:
+    """x float32 power values or complex64 IQ (any shape, contiguous) -> out float32 dB, same
+    shape (unit=True: grey levels 1 + dB / dr_db in [0, 1])."""
+    kind = (DISP_IQ if x.is_complex() else DISP_POWER) | (DISP_UNIT if unit else 0)
     st = lib().display_db(_ptr(_f32view(x)), x.numel(), kind, dr_db, _ptr(ws), ws.numel() * ws.element_size(),
                           _ptr(out), _ptr(peak), _stream())
     _check('display_db', st)
@@ -261,6 +263,15 @@ def mip(vol: torch.Tensor, plane: int, out: torch.Tensor) -> None:
     nz, ny, nx = vol.shape
     st = lib().mip(_ptr(vol), nx, ny, nz, plane, _ptr(out), _stream())
     _check('mip', st)
+
+
+def image_quality(img: torch.Tensor, ref: torch.Tensor, out: torch.Tensor, data_range: float = 1.0) -> None:
+    """img, ref float32 [ny][nx] -> out float64 [3] = (MSE, PSNR, SSIM)."""
+    ny, nx = img.shape
+    if ref.shape != img.shape:
+        raise ValueError('img and ref differ in shape')
+    st = lib().image_quality(_ptr(img), _ptr(ref), nx, ny, data_range, _ptr(out), _stream())
+    _check('image_quality', st)
 
 
 # ----------------------------------------------------------------------------- learned filter

@@ -4,7 +4,8 @@
 // planes).  All passes are HBM-bound streams.
 //
 //   displayed power p = PD (power) or |IQ|^2 (complex IQ; 20 log10 |IQ| = 10 log10 |IQ|^2)
-//   out = max(-dr, 10 log10(p / max p));  max p == 0 shows everything at -dr.
+//   out = max(-dr, 10 log10(p / max p));  max p == 0 shows everything at -dr;
+//   or, as grey levels, 1 + out / dr in [0, 1].
 // The reference max p comes from a two-pass reduction (block maxima, then one block); a
 // maximum does not depend on the order of its operands, so the result is exact and
 // deterministic.  The logarithms use the hardware log2 (error far below 1e-4 dB).
@@ -60,14 +61,15 @@ __global__ void __launch_bounds__(DISP_THREADS) peak_final_kernel(const float* p
 
 template <bool IQ>
 __global__ void __launch_bounds__(DISP_THREADS) db_kernel(const float* in, int64_t n, const float* peak, float neg_dr,
-                                                          float* out) {
+                                                          int unit, float* out) {
     const float pk = *peak;
     const float lpk = __builtin_amdgcn_logf(pk);   // log2
     for (int64_t i = (int64_t)blockIdx.x * DISP_THREADS + threadIdx.x; i < n; i += (int64_t)gridDim.x * DISP_THREADS) {
         const float p = power_at<IQ>(in, i);
         float d = neg_dr;
         if (pk > 0.0f && p > 0.0f) d = fmaxf(neg_dr, TEN_LOG10_2 * (__builtin_amdgcn_logf(p) - lpk));
-        out[i] = d;
+        // grey level (d + dr) / dr: exactly 0 at the floor and 1 at the peak
+        out[i] = unit ? (d - neg_dr) / -neg_dr : d;
     }
 }
 
@@ -116,7 +118,9 @@ extern "C" size_t display_workspace_size(int64_t n) {
 extern "C" int display_db(const float* in, int64_t n, int32_t kind, float dr_db, void* ws, size_t ws_bytes, float* out,
                           float* peak, void* stream) {
     FQ_REQUIRE(n >= 1, "n must be >= 1");
-    FQ_REQUIRE(kind == FQ_DISP_POWER || kind == FQ_DISP_IQ, "kind must be FQ_DISP_POWER or FQ_DISP_IQ");
+    const bool unit = (kind & FQ_DISP_UNIT) != 0;
+    kind &= ~FQ_DISP_UNIT;
+    FQ_REQUIRE(kind == FQ_DISP_POWER || kind == FQ_DISP_IQ, "kind must be FQ_DISP_POWER or FQ_DISP_IQ (| FQ_DISP_UNIT)");
     FQ_REQUIRE(dr_db > 0.0f && dr_db < 1000.0f, "dr_db must be in (0, 1000)");
     FQ_REQUIRE(in && out && ws && aligned16(in) && aligned16(out) && aligned16(ws), "null or misaligned pointer");
     if (ws_bytes < display_workspace_size(n)) {
@@ -135,9 +139,9 @@ extern "C" int display_db(const float* in, int64_t n, int32_t kind, float dr_db,
     hipLaunchKernelGGL(peak_final_kernel, dim3(1), dim3(DISP_THREADS), 0, s, part, nb, pk);
     FQ_LAUNCH_CHECK();
     if (kind == FQ_DISP_IQ)
-        hipLaunchKernelGGL(db_kernel<true>, dim3(nb), dim3(DISP_THREADS), 0, s, in, n, pk, -dr_db, out);
+        hipLaunchKernelGGL(db_kernel<true>, dim3(nb), dim3(DISP_THREADS), 0, s, in, n, pk, -dr_db, unit ? 1 : 0, out);
     else
-        hipLaunchKernelGGL(db_kernel<false>, dim3(nb), dim3(DISP_THREADS), 0, s, in, n, pk, -dr_db, out);
+        hipLaunchKernelGGL(db_kernel<false>, dim3(nb), dim3(DISP_THREADS), 0, s, in, n, pk, -dr_db, unit ? 1 : 0, out);
     FQ_LAUNCH_CHECK();
     return FQ_OK;
 }

@@ -85,7 +85,7 @@ def test_invalid_arguments_return_status(lib):
     assert st == 1 and b'n_modes' in L.fq_last_error()
     st = L.spatial_similarity(None, 10, 20, None, 4, None, 0, None, None, None)
     assert st == 1 and b'null' in L.fq_last_error()
-    st = L.display_db(None, 10, 2, 60.0, None, 0, None, None, None)
+    st = L.display_db(None, 10, 4, 60.0, None, 0, None, None, None)
     assert st == 1 and b'kind' in L.fq_last_error()
     st = L.display_db(None, 10, 0, -5.0, None, 0, None, None, None)
     assert st == 1 and b'dr_db' in L.fq_last_error()
@@ -93,3 +93,7 @@ def test_invalid_arguments_return_status(lib):
     assert st == 1 and b'plane' in L.fq_last_error()
     st = L.mip(None, 0, 4, 4, 0, None, None)
     assert st == 1 and b'size' in L.fq_last_error()
+    st = L.image_quality(None, None, 10, 64, 1.0, None, None)
+    assert st == 1 and b'window' in L.fq_last_error()
+    st = L.image_quality(None, None, 64, 64, 0.0, None, None)
+    assert st == 1 and b'data_range' in L.fq_last_error()
