@@ -100,6 +100,46 @@ int rf_synth(const fq_probe* probe, const fq_tx* tx, const fq_pulse* pulse, int3
              int32_t n_samples, int32_t accumulate, float* rf, void* stream);
 
 /* ---------------------------------------------------------------------------------
+ * fd_synth -- frequency-domain RF synthesis (Appendix D, Eq. 1 and Eq. 2; Algorithm 2):
+ * every scatterer is a monopole; per frequency sample f_j = j df (df = fs / N,
+ * N = n_samples + 2 ceil(6 s fs), s the pulse's Gaussian sigma) the element response is
+ *   H_e(s, f) = (1/v) sum over the v = n_sub_x n_sub_y sub-elements (centres of a regular
+ *               subdivision of the w_x x w_y element) of
+ *               (r_ref / r) e^{(i k - alpha) r} sinc(k b_x u_x) sinc(k b_y u_y),
+ *   k = 2 pi f / c, b the sub-element half-widths, u the direction cosines towards the
+ *   scatterer, sinc(x) = sin(x)/x (w = 0: no directivity), alpha from atten_db_cm_mhz;
+ * transmit a gives the field T_a(s, f) = sum_e W_e e^{i 2 pi f dtau_ae} H_e(s, f) at
+ * scatterer s (dtau of the plane-wave law of rf_synth, W = apod or 1), the echo at element
+ * m is P_a(m, f) = sum_s H_m(s, f) R_s T_a(s, f), and
+ *   rf[f][a][m][t] (=, or += with accumulate) = 2 Re sum_j q_j S(f_j) df P_a(m, f_j) e^{-i 2 pi j t / N}
+ * with S the Fourier transform of the Gaussian pulse of rf_synth (q = 1/2 at j = 0 and
+ * N/2) over the samples j whose S is at least spectral_floor x max S.  No elevation lens
+ * (matrix array).  Scatterers with z <= 0 are ignored.
+ *  pos, pos_static, amp, n_samples, accumulate, rf: as rf_synth (static scatterers are
+ *     transformed once and written to every frame);
+ *  apod  float32 [n_elem] transmit apodization, or NULL (all 1);
+ *  ws    workspace; the scatterers are processed in blocks sized to fit it (the memory
+ *        partition of Algorithm 2): fd_workspace_size(..., B) bytes hold blocks of B
+ *        scatterers (B >= 256 is the minimum); results do not depend on the block size
+ *        beyond FP32 summation order.
+ *  FP64 geometry and phases at the start of every 4-frequency chunk, FP32 stepping and
+ *  accumulation.  Errors: FQ_E_INVALID (parameters, band over 4096 samples),
+ *  FQ_E_WORKSPACE.
+ * ------------------------------------------------------------------------------- */
+typedef struct {
+    double elem_width_x, elem_width_y;   /* element size, m (0: point elements) */
+    int32_t n_sub_x, n_sub_y;            /* sub-elements per element, product 1..64 */
+    double atten_db_cm_mhz;              /* attenuation, dB / (cm MHz); 0: lossless */
+    double spectral_floor;               /* frequency samples kept: S >= floor x max S */
+} fq_fd_params;
+size_t fd_workspace_size(const fq_probe* probe, const fq_tx* tx, const fq_pulse* pulse,
+                         const fq_fd_params* fd, int32_t n_samples, int64_t scatterers_per_block);
+int fd_synth(const fq_probe* probe, const fq_tx* tx, const fq_pulse* pulse, const fq_fd_params* fd,
+             int32_t n_frames, int64_t n_scat, const float* pos, int32_t pos_static,
+             const float* amp, const float* apod, int32_t n_samples, int32_t accumulate, void* ws,
+             size_t ws_bytes, float* rf, void* stream);
+
+/* ---------------------------------------------------------------------------------
  * das_beamform -- rf2iq then delay-and-sum with coherent compounding (Section 2.4.1,
  * Algorithm 3: per-transmit delay application reused for every frame, mean over
  * transmits, voxels processed independently in chunks).

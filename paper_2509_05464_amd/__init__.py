@@ -9,7 +9,8 @@ this package is the thin Python binding over it.
 from ._lib import (  # noqa: F401
     FQ_MAX_ANGLES, FQ_MAX_NT, FQ_SSM_MAX_MODES, LCF_N_PARAM, FqError, CUTOFF_KNEE, CUTOFF_SSM, DISP_POWER, DISP_IQ, MIP_XY, MIP_XZ, MIP_YZ,
     GRAM_FP32, GRAM_SPLIT_BF16, GRAM_BF16, GRAM_SPLIT4_BF16, INTERP_LINEAR, INTERP_HERMITE,
-    Probe, Tx, Grid, Pulse, make_probe, make_tx, make_grid, make_pulse, lib,
+    Probe, Tx, Grid, Pulse, FdParams, make_probe, make_tx, make_grid, make_pulse, make_fd_params, lib,
+    fd_workspace_size, fd_synth,
     rf_synth, das_workspace_size, das_beamform, das_demodulate, das_delay_sum, gram_workspace_size, casorati_gram,
     svd_workspace_size, svd_clutter_filter, hermitian_eig, power_doppler, ssm_workspace_size, spatial_similarity,
     display_workspace_size, display_db, mip, image_quality,

@@ -55,6 +55,16 @@ class Pulse(ctypes.Structure):
     _fields_ = [('n_cycles', ctypes.c_double), ('trunc_sigmas', ctypes.c_double), ('r_ref_m', ctypes.c_double)]
 
 
+class FdParams(ctypes.Structure):
+    _fields_ = [('elem_width_x', ctypes.c_double), ('elem_width_y', ctypes.c_double),
+                ('n_sub_x', ctypes.c_int32), ('n_sub_y', ctypes.c_int32),
+                ('atten_db_cm_mhz', ctypes.c_double), ('spectral_floor', ctypes.c_double)]
+
+
+def make_fd_params(elem_width=(0.0, 0.0), n_sub=(1, 1), atten_db_cm_mhz=0.0, spectral_floor=1e-7) -> FdParams:
+    return FdParams(elem_width[0], elem_width[1], n_sub[0], n_sub[1], atten_db_cm_mhz, spectral_floor)
+
+
 def make_probe(nx_el, ny_el, pitch_x, pitch_y, fc, fs, c) -> Probe:
     return Probe(nx_el, ny_el, pitch_x, pitch_y, fc, fs, c)
 
@@ -85,6 +95,9 @@ _vp, _i32, _i64, _f32, _sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ct
 
 _SIGS = {
     'rf_synth': (ctypes.c_int, [_P(Probe), _P(Tx), _P(Pulse), _i32, _i64, _vp, _i32, _vp, _i32, _i32, _vp, _vp]),
+    'fd_workspace_size': (_sz, [_P(Probe), _P(Tx), _P(Pulse), _P(FdParams), _i32, _i64]),
+    'fd_synth': (ctypes.c_int, [_P(Probe), _P(Tx), _P(Pulse), _P(FdParams), _i32, _i64, _vp, _i32, _vp, _vp, _i32, _i32,
+                                _vp, _sz, _vp, _vp]),
     'das_workspace_size': (_sz, [_P(Probe), _P(Tx), _i32, _i32, _i32]),
     'das_beamform': (ctypes.c_int, [_P(Probe), _P(Tx), _P(Grid), _i32, _i32, _vp, _i32, _vp, _sz, _vp, _vp]),
     'das_demodulate': (ctypes.c_int, [_P(Probe), _P(Tx), _i32, _i32, _vp, _vp, _sz, _vp]),
@@ -160,6 +173,24 @@ def rf_synth(probe: Probe, tx: Tx, pulse: Pulse, pos: torch.Tensor, amp: torch.T
     st = lib().rf_synth(ctypes.byref(probe), ctypes.byref(tx), ctypes.byref(pulse), F, S, _ptr(pos),
                         int(pos_static), _ptr(amp), T, int(accumulate), _ptr(rf), _stream())
     _check('rf_synth', st)
+
+
+def fd_workspace_size(probe: Probe, tx: Tx, pulse: Pulse, fdp: FdParams, n_samples: int,
+                      scatterers_per_block: int) -> int:
+    return lib().fd_workspace_size(ctypes.byref(probe), ctypes.byref(tx), ctypes.byref(pulse), ctypes.byref(fdp),
+                                   n_samples, scatterers_per_block)
+
+
+def fd_synth(probe: Probe, tx: Tx, pulse: Pulse, fdp: FdParams, pos: torch.Tensor, amp: torch.Tensor,
+             rf: torch.Tensor, ws: torch.Tensor, pos_static: bool = False, accumulate: bool = False,
+             apod: Optional[torch.Tensor] = None) -> None:
+    """pos float32 [F or 1][S][3], amp [S] -> rf float32 [F][A][E][T] (frequency-domain model)."""
+    F, A, E, T = rf.shape
+    n_scat = amp.numel()
+    st = lib().fd_synth(ctypes.byref(probe), ctypes.byref(tx), ctypes.byref(pulse), ctypes.byref(fdp), F, n_scat,
+                        _ptr(pos) if n_scat else None, int(pos_static), _ptr(amp) if n_scat else None, _ptr(apod), T,
+                        int(accumulate), _ptr(ws), ws.numel() * ws.element_size(), _ptr(rf), _stream())
+    _check('fd_synth', st)
 
 
 def das_workspace_size(probe: Probe, tx: Tx, n_frames: int, n_samples: int, minimum: bool = False) -> int:

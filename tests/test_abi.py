@@ -55,6 +55,12 @@ def test_workspace_queries_without_gpu(lib):
     assert full == blk * 25 and blk == acq.n_angles * acq.n_elem * acq.n_samples * 8 * 8
     assert fq.gram_workspace_size(acq.n_vox, acq.n_frames, 0) > 0
     assert fq.svd_workspace_size(acq.n_vox, acq.n_frames) > 0
+    pulse = fq.make_pulse()
+    fdp = fq.make_fd_params((0.27e-3, 0.27e-3), (2, 2), 0.5)
+    small = fq.fd_workspace_size(probe, tx, pulse, fdp, acq.n_samples, 256)
+    big = fq.fd_workspace_size(probe, tx, pulse, fdp, acq.n_samples, 70000)
+    assert 0 < small < big
+    assert fq.fd_workspace_size(probe, tx, pulse, fq.make_fd_params(n_sub=(0, 1)), acq.n_samples, 256) == 0
     # the SSM pass: 512 workgroup partials of a 64 x 64 Gram plus 64 column sums at most,
     # and the filter's workspace covers it
     ssm = fq.ssm_workspace_size(acq.n_vox, acq.n_frames)
@@ -97,3 +103,11 @@ def test_invalid_arguments_return_status(lib):
     assert st == 1 and b'window' in L.fq_last_error()
     st = L.image_quality(None, None, 64, 64, 0.0, None, None)
     assert st == 1 and b'data_range' in L.fq_last_error()
+    import ctypes
+    probe = fq.make_probe(4, 4, 3e-4, 3e-4, 7.8e6, 31.25e6, 1540.0)
+    tx = fq.make_tx([(0.0, 0.0)])
+    pulse = fq.make_pulse()
+    bad = fq.make_fd_params(spectral_floor=0.0)
+    st = L.fd_synth(ctypes.byref(probe), ctypes.byref(tx), ctypes.byref(pulse), ctypes.byref(bad), 1, 1, None, 0,
+                    None, None, 64, 0, None, 0, None, None)
+    assert st == 1 and b'spectral_floor' in L.fq_last_error()
