@@ -203,6 +203,62 @@ def rf_only(cfg, args, fq, torch, dev):
                       'tflops': RF_FLOP_PER_TAP * taps / (ms / 1e3) / 1e12}))
 
 
+def fd_only(cfg, args, fq, torch, dev):
+    """Frequency-domain RF synthesis of the workload's scene (element 0.27 mm, 2 x 2
+    sub-elements, 0.5 dB/(cm MHz)), frame by frame: per frame the transmit field and the
+    echo are contractions over scatterer x sub-element x frequency x transmit."""
+    from fqscene import make_scene
+    acq = cfg.acq
+    sc = make_scene(cfg)
+    frames = acq.n_frames if args.fd_frames is None else args.fd_frames
+    probe = fq.make_probe(acq.nx_el, acq.ny_el, acq.pitch, acq.pitch, acq.fc, acq.fs, acq.c)
+    tx = fq.make_tx(acq.tilts_rad())
+    pulse = fq.make_pulse(2.0, 5.0, 1e-3)
+    fdp = fq.make_fd_params((0.9 * acq.pitch, 0.9 * acq.pitch), (2, 2), 0.5, 1e-7)
+    t_pos = torch.from_numpy(np.ascontiguousarray(sc.tissue_pos[:frames] if not sc.tissue_static
+                                                  else sc.tissue_pos)).to(dev)
+    b_pos = torch.from_numpy(np.ascontiguousarray(sc.blood_pos[:frames])).to(dev)
+    t_amp = torch.from_numpy(sc.tissue_amp).to(dev)
+    b_amp = torch.from_numpy(sc.blood_amp).to(dev)
+    if not sc.tissue_static:
+        t_pos = torch.cat([t_pos, b_pos], dim=1).contiguous()
+        t_amp = torch.cat([t_amp, b_amp]).contiguous()
+    n_all = t_amp.numel()
+    ws = torch.empty(fq.fd_workspace_size(probe, tx, pulse, fdp, acq.n_samples, n_all), dtype=torch.uint8, device=dev)
+    rf = torch.empty((frames, acq.n_angles, acq.n_elem, acq.n_samples), dtype=torch.float32, device=dev)
+
+    def run():
+        fq.fd_synth(probe, tx, pulse, fdp, t_pos, t_amp, rf, ws, pos_static=sc.tissue_static, accumulate=False)
+        if sc.tissue_static:
+            fq.fd_synth(probe, tx, pulse, fdp, b_pos, b_amp, rf, ws, pos_static=False, accumulate=True)
+
+    for _ in range(args.warmup):
+        run()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        run()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    # frequency band of the model (as the library selects it)
+    sig = 2.0 / (2.0 * np.sqrt(2.0 * np.log(2.0)) * acq.fc)
+    N = acq.n_samples + 2 * int(np.ceil(6.0 * sig * acq.fs))
+    f = np.arange(N // 2 + 1) * acq.fs / N
+    a2 = 2 * np.pi ** 2 * sig ** 2
+    S = np.exp(-a2 * (f - acq.fc) ** 2) + np.exp(-a2 * (f + acq.fc) ** 2)
+    K = int((S >= 1e-7 * S.max()).sum())
+    scat_frames = (sc.tissue_amp.size if sc.tissue_static else 0) + \
+        (sc.blood_amp.size * frames if sc.tissue_static else n_all * frames)
+    units = scat_frames * acq.n_elem * K * acq.n_angles          # scatterer x element x frequency x transmit
+    flop = 16.0 * units                                            # two complex multiply-adds (field, echo)
+    print(json.dumps({'kernel': 'fd_synth', 'workload': cfg.name, 'frames': frames, 'frequency_samples': K,
+                      'sub_elements': 4, 'ms': ms, 'ms_per_frame': ms / frames,
+                      'gunits_per_s': units / (ms / 1e3) / 1e9,
+                      'contraction_tflops': flop / (ms / 1e3) / 1e12}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument('--gpus', type=int, default=1)
@@ -211,10 +267,12 @@ def main():
     ap.add_argument('--config', default='c2')
     ap.add_argument('--no-cpu-baseline', action='store_true')
     ap.add_argument('--no-truth', action='store_true', help='skip the untimed ground-truth error pass')
-    ap.add_argument('--only', choices=['das', 'rf'], default=None,
+    ap.add_argument('--fd-frames', type=int, default=None, help='frames of the frequency-domain run (--only fd)')
+    ap.add_argument('--only', choices=['das', 'rf', 'fd'], default=None,
                     help='das: the delay-and-sum kernel alone on the workload geometry (seeded random RF), '
                          'plus a 2 GiB device copy that calibrates byte counters; rf: RF synthesis of the '
-                         'workload scene alone; for profiler runs')
+                         'workload scene alone; fd: frequency-domain RF synthesis of the workload scene; '
+                         'for profiler runs')
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({'error': 'this build runs on one GPU; --gpus must be 1 (multi-GPU sharding is '
@@ -234,6 +292,8 @@ def main():
         return das_only(cfg, args, fq, torch, dev)
     if args.only == 'rf':
         return rf_only(cfg, args, fq, torch, dev)
+    if args.only == 'fd':
+        return fd_only(cfg, args, fq, torch, dev)
 
     _log(f'[bench] scene {cfg.name}')
     sc = make_scene(cfg)
