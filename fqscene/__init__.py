@@ -7,6 +7,6 @@ reflectivities), plus seeded random RF / IQ arrays used as stage inputs.
 It holds none of the reconstruction arithmetic (no delays, no pulse model,
 no demodulation, no beamforming, no clutter filtering).
 """
-from .configs import Acq, SceneSpec, CONFIGS, MOTION_SWEEP, get_config, motion_sweep_configs  # noqa: F401
+from .configs import Acq, SceneSpec, CONFIGS, MOTION_SWEEP, augmented_motion_config, get_config, motion_sweep_configs  # noqa: F401
 from .scene import Scene, make_scene, rigid_motion, tissue_displacement  # noqa: F401
 from .random_inputs import random_rf, random_casorati, lcf_init_weights, batch_indices  # noqa: F401

@@ -190,6 +190,25 @@ MOTION_SWEEP = (
 )
 
 
+def augmented_motion_config(base: str, seed: int) -> Config:
+    """The base workload with a seeded steady tissue motion, for training data that spans
+    the motion sweep's range: even seeds a constant velocity (0.5-10 mm/s, uniform
+    direction), odd seeds a rotation about -y (0.05-0.5 rad/s about a centre 15-35 mm
+    deep).  The scene itself is drawn with the same seed."""
+    import numpy as np
+    b = CONFIGS[base]
+    rng = np.random.default_rng(seed + 7_777_777)
+    if seed % 2 == 0:
+        d = rng.standard_normal(3)
+        d /= np.linalg.norm(d)
+        v = tuple(float(x) for x in d * rng.uniform(0.5e-3, 10e-3))
+        sc = dataclasses.replace(b.scene, seed=seed, motion='velocity', velocity=v)
+    else:
+        sc = dataclasses.replace(b.scene, seed=seed, motion='rotation', rot_omega=float(rng.uniform(0.05, 0.5)),
+                                 rot_centre=(0.0, 0.0, float(rng.uniform(15e-3, 35e-3))))
+    return dataclasses.replace(b, name=f'{base}_aug{seed}', scene=sc)
+
+
 def motion_sweep_configs(base: str = 'c4_train', seed: int = 3000) -> dict:
     """name -> Config of the motion sweep, one seeded scene recipe for every case."""
     b = CONFIGS[base]

@@ -28,7 +28,9 @@ from .train_lcf import make_pair
 
 DR_DB = 60.0
 PLANES = (('xy', fq.MIP_XY), ('xz', fq.MIP_XZ), ('yz', fq.MIP_YZ))
-WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), 'weights', 'lcf_c4.npz')
+# the network trained with steady-motion variants of the training scenes (the sweep's regime);
+# lcf_c4.npz is trained on cardiac/respiratory motion only
+WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), 'weights', 'lcf_c4_motion.npz')
 
 
 class _Viewer:
@@ -122,13 +124,14 @@ def run_case(cfg, filt: LearnedFilter, dev: torch.device, keep_mips: bool = Fals
 
 
 def run_sweep(cases: Optional[Sequence[str]] = None, frames: Optional[int] = None, device=None,
-              verbose: bool = True, keep_mips: bool = False) -> list:
+              verbose: bool = True, keep_mips: bool = False, weights: Optional[str] = None) -> list:
     from fqscene import MOTION_SWEEP, lcf_init_weights, motion_sweep_configs
     from fqscene.configs import scaled
     dev = device or torch.device('cuda')
     cfgs = motion_sweep_configs()
     names = list(cases) if cases else [n for n, _ in MOTION_SWEEP]
-    filt = LearnedFilter.load(WEIGHTS, dev) if os.path.exists(WEIGHTS) else LearnedFilter(lcf_init_weights(0), dev)
+    wpath = weights or WEIGHTS
+    filt = LearnedFilter.load(wpath, dev) if os.path.exists(wpath) else LearnedFilter(lcf_init_weights(0), dev)
     out = []
     for n in names:
         cfg = cfgs[n] if frames is None else scaled(cfgs[n], frames=frames)
@@ -147,8 +150,9 @@ def main():
     ap.add_argument('--cases', default=None, help='comma-separated subset of the motion cases')
     ap.add_argument('--frames', type=int, default=None)
     ap.add_argument('--json', default=None)
+    ap.add_argument('--weights', default=None, help='learned-filter weights (.npz); default the motion-trained network')
     args = ap.parse_args()
-    res = run_sweep(args.cases.split(',') if args.cases else None, args.frames)
+    res = run_sweep(args.cases.split(',') if args.cases else None, args.frames, weights=args.weights)
     if args.json:
         with open(args.json, 'w') as fh:
             json.dump(res, fh, indent=1)

@@ -41,18 +41,24 @@ def make_pair(cfg, scene, rf: torch.Tensor, ws: torch.Tensor, mix_out: torch.Ten
     fq.das_beamform(probe, tx, grid, rf, mix_out, ws, fq.INTERP_LINEAR)
 
 
-def make_pairs(cfg, seeds: Sequence[int], device=None):
-    from fqscene import make_scene
+def make_pairs(cfg, seeds: Sequence[int], device=None, aug_seeds: Sequence[int] = ()):
+    """Pairs of the workload's scenes for `seeds`, then of its seeded steady-motion variants
+    (augmented_motion_config) for `aug_seeds`; all share the acquisition geometry."""
+    from fqscene import augmented_motion_config, make_scene
     device = device or torch.device('cuda')
     acq = cfg.acq
     F, NV = acq.n_frames, acq.n_vox
     probe, tx, _, _ = _structs(acq)
     rf = torch.empty((F, acq.n_angles, acq.n_elem, acq.n_samples), dtype=torch.float32, device=device)
     ws = torch.empty(fq.das_workspace_size(probe, tx, F, acq.n_samples), dtype=torch.uint8, device=device)
-    mix = torch.empty((len(seeds), F, NV), dtype=torch.complex64, device=device)
+    n = len(seeds) + len(aug_seeds)
+    mix = torch.empty((n, F, NV), dtype=torch.complex64, device=device)
     blood = torch.empty_like(mix)
     for i, sd in enumerate(seeds):
         make_pair(cfg, make_scene(cfg, seed=sd), rf, ws, mix[i], blood[i])
+    for i, sd in enumerate(aug_seeds):
+        acfg = augmented_motion_config(cfg.name, sd)
+        make_pair(acfg, make_scene(acfg), rf, ws, mix[len(seeds) + i], blood[len(seeds) + i])
     del rf, ws
     return mix, blood
 
@@ -111,6 +117,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument('--config', default='c4_train')
     ap.add_argument('--seeds', default='1000-1063')
+    ap.add_argument('--aug-seeds', default=None, help='seed range of steady-motion variants added to the training set')
     ap.add_argument('--steps', type=int, default=3000)
     ap.add_argument('--batch', type=int, default=4096)
     ap.add_argument('--lr', type=float, default=1e-3)
@@ -122,9 +129,13 @@ def main():
     lo, hi = (int(v) for v in args.seeds.split('-'))
     cfg = get_config(args.config)
     t0 = time.time()
-    mix, blood = make_pairs(cfg, list(range(lo, hi + 1)))
+    aug = []
+    if args.aug_seeds:
+        alo, ahi = (int(v) for v in args.aug_seeds.split('-'))
+        aug = list(range(alo, ahi + 1))
+    mix, blood = make_pairs(cfg, list(range(lo, hi + 1)), aug_seeds=aug)
     torch.cuda.synchronize()
-    print(f'[train] {hi - lo + 1} pairs in {time.time() - t0:.1f}s', flush=True)
+    print(f'[train] {mix.shape[0]} pairs in {time.time() - t0:.1f}s', flush=True)
     filt = LearnedFilter(lcf_init_weights(args.init_seed), lr=args.lr)
     train(filt, mix, blood, args.steps, args.batch)
     filt.save(args.out)
