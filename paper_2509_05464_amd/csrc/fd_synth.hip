@@ -19,10 +19,10 @@
 //   fd_idft_kernel workgroup = (element, transmit): the weighted inverse transform of the
 //                  band, the complex exponential stepped in frequency and re-anchored
 //                  from an exact integer phase every 64 samples.
-// Within a chunk e^{i k r} and the directivity sines are stepped from frequency to
-// frequency by one complex multiplication (the frequency-stepping propagation update of
-// Algorithm 2); each chunk starts from phases taken in FP64 (cycles = j df r / c) so the
-// error does not grow with j.  Scatterer blocks bound the transmit-field buffer by the
+// Within a chunk e^{i k r} is stepped from frequency to frequency by one complex
+// multiplication (the frequency-stepping propagation update of Algorithm 2); each chunk
+// starts from phases taken in FP64 (cycles = j df r / c) so the error does not grow with
+// j.  The directivity sines (a few cycles at most) come straight from the hardware sine.  Scatterer blocks bound the transmit-field buffer by the
 // workspace (the memory partition of Algorithm 2); their echoes add up in P.
 #include "fq_common.hpp"
 
@@ -97,6 +97,8 @@ __device__ __forceinline__ void elem_resp(const FdArgs& a, double ex, double ey,
             }
             z.x *= g;
             z.y *= g;
+            // directivity sinc(2 pi j t) = sin(2 pi j t) / (2 pi j t), t = b df u / c cycles per
+            // frequency step: the sine straight from the hardware (argument reduced to a turn)
             float dxq[KC], dyq[KC];
 #pragma unroll
             for (int q = 0; q < KC; ++q) dxq[q] = dyq[q] = 1.0f;
@@ -104,26 +106,22 @@ __device__ __forceinline__ void elem_resp(const FdArgs& a, double ex, double ey,
             if (a.wx > 0.0) {
                 const float tx = (float)(a.bx_df_c * dx) * rinv;   // directivity cycles per step
                 if (tx != 0.0f) {
-                    float2 zx = cis_cycles((double)tx * j0);
-                    const float2 sxs = cis_cycles((double)tx);
                     const float ix = __builtin_amdgcn_rcpf((float)TWO_PI * tx);
 #pragma unroll
                     for (int q = 0; q < KC; ++q) {
-                        dxq[q] = invj[q] > 0.0f ? zx.y * ix * invj[q] : 1.0f;
-                        zx = cmul(zx, sxs);
+                        const float c = tx * (float)(j0 + q);
+                        dxq[q] = invj[q] > 0.0f ? __builtin_amdgcn_sinf(c - floorf(c)) * ix * invj[q] : 1.0f;
                     }
                 }
             }
             if (a.wy > 0.0) {
                 const float ty = (float)(a.by_df_c * dy) * rinv;
                 if (ty != 0.0f) {
-                    float2 zy = cis_cycles((double)ty * j0);
-                    const float2 sys = cis_cycles((double)ty);
                     const float iy = __builtin_amdgcn_rcpf((float)TWO_PI * ty);
 #pragma unroll
                     for (int q = 0; q < KC; ++q) {
-                        dyq[q] = invj[q] > 0.0f ? zy.y * iy * invj[q] : 1.0f;
-                        zy = cmul(zy, sys);
+                        const float c = ty * (float)(j0 + q);
+                        dyq[q] = invj[q] > 0.0f ? __builtin_amdgcn_sinf(c - floorf(c)) * iy * invj[q] : 1.0f;
                     }
                 }
             }
