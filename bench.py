@@ -266,6 +266,7 @@ def main():
     ap.add_argument('--warmup', type=int, default=1)
     ap.add_argument('--config', default='c2')
     ap.add_argument('--no-cpu-baseline', action='store_true')
+    ap.add_argument('--serial', action='store_true', help='run the filters after the beamformer on one stream')
     ap.add_argument('--no-truth', action='store_true', help='skip the untimed ground-truth error pass')
     ap.add_argument('--fd-frames', type=int, default=None, help='frames of the frequency-domain run (--only fd)')
     ap.add_argument('--only', choices=['das', 'rf', 'fd'], default=None,
@@ -350,49 +351,63 @@ def main():
 
     stages = ['rf_synth', 'rf2iq', 'das', 'gram_fp32', 'svd_fp32', 'gram_split_bf16', 'svd_split_bf16',
               'lcf_infer', 'fallback', 'lcf_train_step']
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(len(stages) + 1)]
+    ev_b = {n: torch.cuda.Event(enable_timing=True) for n in stages}
+    ev_e = {n: torch.cuda.Event(enable_timing=True) for n in stages}
+    # after the beamformer, the FP32 SVD filter, the split-BF16 SVD filter and the learned
+    # filter only read the IQ: three streams of default priority (their eigensolvers are
+    # single-workgroup latency chains that the learned filter's inference fills around)
+    s_main = torch.cuda.current_stream()
+    side = (s_main,) * 3 if args.serial else tuple(torch.cuda.Stream() for _ in range(3))
+    gws2 = torch.empty_like(gws)
+    iq_ready, svd_done, split_done, lcf_done = (torch.cuda.Event() for _ in range(4))
 
-    def step(record: bool):
+    def stage(name, record, fn):
         if record:
-            ev[0].record()
+            ev_b[name].record()
+        fn()
+        if record:
+            ev_e[name].record()
+
+    def synth():
         if t_static:
             fq.rf_synth(probe, tx, pulse, t_pos, t_amp, rf, pos_static=True, accumulate=False)
             fq.rf_synth(probe, tx, pulse, b_pos, b_amp, rf, pos_static=False, accumulate=True)
         else:
             fq.rf_synth(probe, tx, pulse, all_pos, all_amp, rf, pos_static=False, accumulate=False)
-        if record:
-            ev[1].record()
-        fq.das_demodulate(probe, tx, rf, das_ws)
-        if record:
-            ev[2].record()
-        fq.das_delay_sum(probe, tx, grid, T, das_ws, iq, fq.INTERP_LINEAR)
-        if record:
-            ev[3].record()
-        fq.casorati_gram(iq, G, gws, fq.GRAM_FP32)
-        if record:
-            ev[4].record()
-        fq.svd_clutter_filter(iq, G, sws, sigma, k1, cfg.cutoff, pd=pd_svd, status=st1)
-        if record:
-            ev[5].record()
-        fq.casorati_gram(iq, G2, gws, fq.GRAM_SPLIT4_BF16)
-        if record:
-            ev[6].record()
-        fq.svd_clutter_filter(iq, G2, sws2, sigma2, k2, cfg.cutoff, pd=pd_split, status=st2)
-        if record:
-            ev[7].record()
-        filt.infer(iq, pd_lcf)
-        if record:
-            ev[8].record()
-        fq.lcf_fallback(pd_lcf, pd_svd, pd_out, fb_flag, fb_d, fb_ws, -10.0)
-        if record:
-            ev[9].record()
+
+    def train():
         idx = idx_host[step_no[0] % len(idx_host)]
         step_no[0] += 1
         fq.lcf_gather(tr_mix, idx, xb)
         fq.lcf_gather(tr_blood, idx, yb)
         filt.train_step(xb, yb)
-        if record:
-            ev[10].record()
+
+    def step(record: bool):
+        stage('rf_synth', record, synth)
+        stage('rf2iq', record, lambda: fq.das_demodulate(probe, tx, rf, das_ws))
+        stage('das', record, lambda: fq.das_delay_sum(probe, tx, grid, T, das_ws, iq, fq.INTERP_LINEAR))
+        iq_ready.record()
+        with torch.cuda.stream(side[0]):
+            side[0].wait_event(iq_ready)
+            stage('gram_fp32', record, lambda: fq.casorati_gram(iq, G, gws, fq.GRAM_FP32))
+            stage('svd_fp32', record, lambda: fq.svd_clutter_filter(iq, G, sws, sigma, k1, cfg.cutoff, pd=pd_svd,
+                                                                     status=st1))
+            svd_done.record()
+        with torch.cuda.stream(side[1]):
+            side[1].wait_event(iq_ready)
+            stage('gram_split_bf16', record, lambda: fq.casorati_gram(iq, G2, gws2, fq.GRAM_SPLIT4_BF16))
+            stage('svd_split_bf16', record, lambda: fq.svd_clutter_filter(iq, G2, sws2, sigma2, k2, cfg.cutoff,
+                                                                           pd=pd_split, status=st2))
+            split_done.record()
+        with torch.cuda.stream(side[2]):
+            side[2].wait_event(iq_ready)
+            stage('lcf_infer', record, lambda: filt.infer(iq, pd_lcf))
+            side[2].wait_event(svd_done)
+            stage('fallback', record, lambda: fq.lcf_fallback(pd_lcf, pd_svd, pd_out, fb_flag, fb_d, fb_ws, -10.0))
+            stage('lcf_train_step', record, train)
+            lcf_done.record()
+        for e in (svd_done, split_done, lcf_done):
+            s_main.wait_event(e)
 
     _log('[bench] warmup')
     for _ in range(args.warmup):
@@ -404,7 +419,7 @@ def main():
     for _ in range(args.steps):
         step(True)
         torch.cuda.synchronize()   # per-step sync so every event pair is complete; counted in the step time
-        acc += np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(len(stages))])
+        acc += np.array([ev_b[n].elapsed_time(ev_e[n]) for n in stages])
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms_step = wall / args.steps * 1e3
@@ -465,6 +480,7 @@ def main():
             },
         },
         'stage_ms': stage_ms,
+        'filter_streams': 1 if args.serial else 3,
         'das_gunits_per_s': units / t_das / 1e9,
         'pd_volumes_per_s': {
             'svd_fp32': 1e3 / (stage_ms['gram_fp32'] + stage_ms['svd_fp32']),
