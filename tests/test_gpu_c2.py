@@ -89,3 +89,28 @@ def test_learned_forward_full_size_sampled_series(gpu):
     err = rel_l2(pd.cpu().numpy()[vox], np.mean(np.abs(y) ** 2, axis=0))
     print('c2 learned pd rel L2', err)
     assert err < 4e-3
+
+
+def test_split_bf16_precision_variant_full_size(gpu):
+    """The precision variant at full size (2.1M voxels x 200 frames): the three-product
+    split-BF16 Gram on the matrix cores against its bit-exact FP64 emulation (only the
+    accumulation order differs), and the power Doppler of that path, at the FP32 path's
+    rank, against the FP64 oracle on sampled voxels."""
+    print('c3 split-BF16', flush=True)
+    iq = random_casorati(ACQ.n_vox, ACQ.n_frames, seed=7, rank=4, tissue_db=45)
+    out = gpu_svd_pd(dev(iq), 4, mode=1)
+    G = out['G'].cpu().numpy()
+    Ge = obf16.gram_split_bf16(iq, 3)
+    eg = rel_l2(G, Ge)
+    Go = clutter.gram(iq)
+    e_exact = rel_l2(G, Go)
+    lam, V = clutter.eig_desc(Go)
+    rng = np.random.default_rng(8)
+    vox = rng.integers(0, ACQ.n_vox, 4096)
+    pd_o = clutter.power_doppler(clutter.filter_iq(iq[:, vox].astype(np.complex128), V, 4))
+    ep = rel_l2(out['pd'].cpu().numpy()[vox], pd_o)
+    print('c3 split gram vs emulation', eg, 'vs exact', e_exact, 'pd vs FP64 oracle', ep)
+    assert eg < 1e-6
+    assert e_exact < 1e-4
+    assert ep < 1e-3
+    assert int(out['k'].item()) == 4
