@@ -44,6 +44,28 @@ def _log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def profile_values(name: str):
+    """The 'key: value' block of a committed profile summary, or None when the summary is
+    missing or the kernel sources changed since it was measured."""
+    import hashlib
+    path = os.path.join(ROOT, 'profiles', name)
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if ':' in line and not line.startswith(('#', '|', ' ', '-')):
+            k, v = line.split(':', 1)
+            kv[k.strip()] = v.strip()
+    try:
+        h = hashlib.sha256()
+        for src in kv['sources'].split():
+            with open(os.path.join(ROOT, src), 'rb') as fh:
+                h.update(fh.read())
+        return kv if h.hexdigest() == kv['sources_sha256'] else None
+    except (KeyError, OSError):
+        return None
+
+
 def measured_traffic(name: str):
     """HBM bytes per launch of a kernel from its committed counter summary (FETCH_SIZE and
     WRITE_SIZE runs, each scaled by a copy kernel of known size), or None when the
@@ -477,6 +499,8 @@ def main():
                 'traffic': measured_traffic('rf_synth_c2_hbm_traffic.md') if cfg.name in ('c2', 'c3') else None,
                 'traffic_unit': 'bytes per launch (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, copy-calibrated)',
                 'stage_ms': stage_ms_rf,
+                'valu_issue_per_cu_clock': (lambda kv: float(kv['valu_issue_per_cu_clock']) if kv else None)(
+                    profile_values('rf_synth_c2_sq_counters.md') if cfg.name in ('c2', 'c3') else None),
             },
         },
         'stage_ms': stage_ms,
