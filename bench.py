@@ -298,8 +298,8 @@ def main():
                          'for profiler runs')
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({'error': 'this build runs on one GPU; --gpus must be 1 (multi-GPU sharding is '
-                                   'described in DESIGN.md, not built)'}))
+        print(json.dumps({'error': 'the path runs on one GPU: --gpus must be 1 (sharding across GPUs is designed, '
+                                   'not implemented)'}))
         sys.exit(2)
 
     import torch
