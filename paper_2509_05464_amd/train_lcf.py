@@ -64,15 +64,20 @@ def make_pairs(cfg, seeds: Sequence[int], device=None, aug_seeds: Sequence[int] 
 
 
 def train(filt: LearnedFilter, mix: torch.Tensor, blood: torch.Tensor, steps: int, batch: int, seed: int = 0,
-          log_every: int = 100, verbose: bool = True):
-    """Adam steps on random voxel series of the training volumes.  Returns the loss history."""
+          log_every: int = 100, verbose: bool = True, lr_final: float = None):
+    """Adam steps on random voxel series of the training volumes (constant rate, or a cosine
+    decay from the filter's rate to lr_final).  Returns the loss history."""
+    import math
     from fqscene import batch_indices
     n_vol, F, NV = mix.shape
     x = torch.empty((F, batch), dtype=torch.complex64, device=mix.device)
     y = torch.empty_like(x)
     hist = []
+    lr0 = filt.lr
     t0 = time.time()
     for s in range(steps):
+        if lr_final is not None:
+            filt.lr = lr_final + 0.5 * (lr0 - lr_final) * (1.0 + math.cos(math.pi * s / max(1, steps - 1)))
         idx = torch.from_numpy(batch_indices(n_vol * NV, batch, seed + s)).to(mix.device)
         fq.lcf_gather(mix, idx, x)
         fq.lcf_gather(blood, idx, y)
@@ -121,6 +126,7 @@ def main():
     ap.add_argument('--steps', type=int, default=3000)
     ap.add_argument('--batch', type=int, default=4096)
     ap.add_argument('--lr', type=float, default=1e-3)
+    ap.add_argument('--lr-final', type=float, default=None, help='cosine decay of the rate to this value')
     ap.add_argument('--init-seed', type=int, default=0)
     ap.add_argument('--eval-seed', type=int, default=None)
     ap.add_argument('--eval-config', default=None, help='workload of the held-out volume (default: --config)')
@@ -137,7 +143,7 @@ def main():
     torch.cuda.synchronize()
     print(f'[train] {mix.shape[0]} pairs in {time.time() - t0:.1f}s', flush=True)
     filt = LearnedFilter(lcf_init_weights(args.init_seed), lr=args.lr)
-    train(filt, mix, blood, args.steps, args.batch)
+    train(filt, mix, blood, args.steps, args.batch, lr_final=args.lr_final)
     filt.save(args.out)
     if args.eval_seed is not None:
         del mix, blood
