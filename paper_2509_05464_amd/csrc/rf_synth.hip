@@ -8,7 +8,8 @@
 // end, and for static scatterers to every frame (Algorithm 1 computes the static tissue
 // RF once and reuses it for all frames).
 //
-// Pulse samples.  With nb = floor(x), f = x - nb and tap j at sample nb + j (u = j - f),
+// Pulse samples.  With the even base sample b = 2 floor(x / 2), f = x - b in [0, 2) and
+// tap j at sample b + j (u = j - f),
 //   g(u) = A exp(-u^2 / (2 s^2)) cos(theta u),   theta = 2 pi fc / fs,  s in samples,
 // splits as  g = F_j * e_j  with the lane-independent Gaussian factor
 //   F_j = exp(-j^2 / (2 s^2))
@@ -16,33 +17,43 @@
 // e_j is the real part of a geometric sequence with ratio rho e^{i theta}, so it obeys
 //   e_{j+1} = 2 rho cos(theta) e_j - rho^2 e_{j-1}        (forward)
 //   e_{j-1} = (2 cos(theta) / rho) e_j - rho^-2 e_{j+1}   (backward)
-// Both chains start at the centre (e_0, e_1: cosines of arguments below a quarter
-// turn), so |rho^j| stays within exp(+-J/s^2) and nothing over- or underflows.  A tap
-// costs one multiply, one FMA, one multiply by F_j (a scalar register) and one LDS
-// read-add-write.
+// Both chains start at the centre (e_0, e_1: cosines of arguments below half a turn),
+// so |rho^j| stays within exp(+-2(J+2)/s^2) and nothing over- or underflows.  A tap
+// costs one multiply, one FMA and one FMA with F_j (a scalar register) into the trace.
 //
 // Tap window.  The pulse is kept where |u| <= half (half = truncation x s).  With
-// J = floor(half) and h = half - J, taps j = -J+1 .. J are always inside, tap -J is
-// inside iff f <= h and tap J+1 iff f >= 1 - h; J is a compile-time constant so the
-// 2J+2 taps unroll into straight-line code with immediate LDS offsets.
+// J = floor(half) and h = half - J, taps j = -J+2 .. J are always inside, tap -J is
+// inside iff f <= h, tap -J+1 iff f <= 1 + h, tap J+1 iff f >= 1 - h and tap J+2 iff
+// f >= 2 - h.  The taps are added in aligned pairs of samples (b + j, b + j + 1), j
+// even, with one 8-byte LDS read-add-write per pair: J + 2 pairs, so the chain of
+// dependent LDS round trips per scatterer is half as long as with single samples.  J is
+// a compile-time constant, so the pairs unroll into straight-line code with immediate
+// LDS offsets.
 //
 // Lanes of one instruction must not update the same word, and lanes whose words fall in
-// the same LDS bank serialise.  The LDS serves a 64-lane access as two 32-lane halves
-// over 32 banks, so each round only one lane per residue of nb modulo 32 within each
-// half adds its taps (a 2 x 32-slot claim table in LDS, last writer wins), and a winner
-// of the upper half stands down if the lower half's winner of the same residue has the
-// same nb.  The taps of one instruction then hit distinct words and, per half, distinct
-// banks.  (LDS float atomics would remove the claim but run at a small fraction of the
-// plain access rate.)  Lanes that lose keep their scatterer for the next round and the
-// others load new ones (wave prefix sum over the free lanes).
+// the same LDS bank serialise.  On gfx950 a 64-lane 8-byte LDS read is served as two
+// 32-lane halves over 64 banks (32 bank pairs), an 8-byte write as four 16-lane quarters
+// over 32 banks.  Each round only one lane per residue of the pair index b / 2 modulo 32
+// within each half adds its taps (a 2 x 32-slot claim table in LDS, last writer wins), and
+// a winner of the upper half stands down if the lower half's winner of the same residue
+// has the same pair index.  The pairs of one instruction then hit distinct words, the
+// reads distinct bank pairs; two winners of one quarter whose pair indices differ by 16
+// (mod 32) share a bank pair on the write.  (Claims that also keep the writes apart, or
+// one 4-byte plane per sample parity, cost more issue slots or LDS instructions than
+// these write conflicts cost.)  (LDS float atomics would
+// remove the claim but run at a small fraction of the plain access rate.)  Lanes that
+// lose keep their scatterer for the next round and the others load new ones (wave prefix
+// sum over the free lanes).
 #include "fq_common.hpp"
 
 namespace fq {
 namespace {
 
 constexpr int RF_THREADS = 64;        // one wave per workgroup, one trace per wave
-constexpr int RF_PAD = 64;            // guard band (floats) on each side of the LDS trace
-constexpr int RF_MAX_J = 31;          // floor(half) limit: 2J+2 <= RF_PAD taps
+constexpr int RF_MAX_J = 31;          // floor(half) limit
+// guard band (floats, even) on each side of the LDS trace: taps reach 2J + 5 samples out
+__host__ __device__ constexpr int rf_pad(int J) { return 2 * J + 6; }
+constexpr int RF_MAX_PAD = rf_pad(RF_MAX_J);
 constexpr int RF_LDS_FLOATS = 16384;  // trace + guard bands budget (64 KiB)
 
 struct RfArgs {
@@ -60,17 +71,18 @@ struct RfArgs {
     float nu;               // fc / fs (carrier cycles per sample)
     float two_cos_theta;
     float r_ref;
-    float F[2 * RF_MAX_J + 2];   // F[J + j] = exp(-j^2 / (2 s^2)), j = -J .. J+1
+    float F[2 * RF_MAX_J + 6];   // F[J + 1 + j] = exp(-j^2 / (2 s^2)), j = -J-1 .. J+3
     double ux[FQ_MAX_ANGLES], uy[FQ_MAX_ANGLES], uz[FQ_MAX_ANGLES], t0s[FQ_MAX_ANGLES];  // t0s = t0 * fs
 };
 
 // State of one scatterer record held by a lane between rounds.
 struct Rec {
-    int nb;
+    int nbp;          // pair index b / 2
     float e0, e1;     // e_0, e_1
     float af, bf;     // forward coefficients 2 rho cos(theta), rho^2
     float ab, bb;     // backward coefficients 2 cos(theta) / rho, rho^-2
-    float mlo, mhi;   // inclusion of taps -J and J+1 (0 or 1)
+    float m0, m1;     // inclusion of taps -J and -J+1 (0 or 1)
+    float m2, m3;     // inclusion of taps J+1 and J+2 (0 or 1)
 };
 
 // Delay and pulse set-up of scatterer s for element (pex, pey) and transmit an.
@@ -84,14 +96,16 @@ __device__ __forceinline__ bool make_rec(const RfArgs& a, const float* posf, int
     const double rho = sqrt_nr(dx * dx + dy * dy + pz * pz);
     const double x = (ux * px + uy * py + uz * pz) * a.fs_c - t0s + rho * a.fs_c;
     if (!(x > -(double)(J + 2) && x < (double)(a.T + J + 1))) return false;   // also rejects NaN
-    const double fl = floor(x);
-    const double fd = x - fl;
-    r.nb = (int)fl;
-    r.mlo = fd <= a.h ? 1.0f : 0.0f;
-    r.mhi = fd >= 1.0 - a.h ? 1.0f : 0.0f;
+    const double fl = floor(0.5 * x);
+    const double fd = x - 2.0 * fl;   // in [0, 2)
+    r.nbp = (int)fl;
+    r.m0 = fd <= a.h ? 1.0f : 0.0f;
+    r.m1 = fd <= 1.0 + a.h ? 1.0f : 0.0f;
+    r.m2 = fd >= 1.0 - a.h ? 1.0f : 0.0f;
+    r.m3 = fd >= 2.0 - a.h ? 1.0f : 0.0f;
     const float f = (float)fd;
     const float scale = a.amp[s] * a.r_ref * __builtin_amdgcn_rcpf((float)rho);
-    // exponent arguments lie in [-1/(2 s^2 ln 2), 1/(s^2 ln 2)], far from over/underflow:
+    // exponent arguments lie in [-2/(s^2 ln 2), 2/(s^2 ln 2)], far from over/underflow:
     // the bare hardware exp2 is enough
     const float gc = scale * __builtin_amdgcn_exp2f(a.kexp2 * f * f);
     const float rh = __builtin_amdgcn_exp2f(-2.0f * a.kexp2 * f);   // rho = exp(f / s^2) >= 1
@@ -105,21 +119,36 @@ __device__ __forceinline__ bool make_rec(const RfArgs& a, const float* posf, int
     return true;
 }
 
-// Adds the 2J+2 taps of one record into the trace (tr indexed by sample) with plain
-// LDS read-add-write.  Within one instruction the lanes of a round touch distinct words
-// (distinct nb), but the word a lane updates at one tap can be the word another lane
-// reads at the next tap, so each tap's write must land before the next tap's read is
-// issued: a wave barrier between taps keeps the compiler from hoisting the reads, and
+// Adds the taps of one record into the trace (tr indexed by sample) as J + 2 aligned
+// pairs with plain 8-byte LDS read-add-write.  Within one instruction the lanes of a
+// round touch distinct pairs, but the pair a lane updates at one step can be the pair
+// another lane reads at the next step, so each write must land before the next read is
+// issued: a wave barrier between steps keeps the compiler from hoisting the reads, and
 // the LDS executes one wave's accesses in order.
-__device__ __forceinline__ void add_tap(float* p, float v) {
-    *p += v;
+__device__ __forceinline__ void add_pair(float2* p, float lo, float hi) {
+    float2 v = *p;
+    v.x += lo;
+    v.y += hi;
+    *p = v;
     __builtin_amdgcn_wave_barrier();
+}
+
+// Inclusion mask of tap j (only the four edge taps can be outside the window).
+template <int J>
+__device__ __forceinline__ float tap_mask(const Rec& r, int j) {
+    float m = 1.0f;
+    if (j == -J) m *= r.m0;
+    if (j == -J + 1) m *= r.m1;
+    if (j == J + 1) m *= r.m2;
+    if (j == J + 2) m *= r.m3;
+    return m;
 }
 
 template <int J>
 __device__ __forceinline__ void emit(const RfArgs& a, float* tr, const Rec& r) {
-    float* p = tr + r.nb;
-    // backward chain: j = -J .. -1 (values computed first, added in sample order below)
+    float2* p = reinterpret_cast<float2*>(tr) + r.nbp;   // samples b, b + 1
+    constexpr int P0 = (J & 1) ? -J - 1 : -J;              // first (even) pair start
+    // backward chain: taps j = -1 .. -J (values first, added in sample order below)
     float vb[J > 0 ? J : 1];
     {
         float em = r.e1, ec = r.e0;
@@ -128,39 +157,47 @@ __device__ __forceinline__ void emit(const RfArgs& a, float* tr, const Rec& r) {
             const float en = fmaf(r.ab, ec, -(r.bb * em));
             em = ec;
             ec = en;
-            float v = a.F[J + j] * en;
-            if (j == -J) v *= r.mlo;
-            vb[-j - 1] = v;
+            vb[-j - 1] = a.F[J + 1 + j] * en * tap_mask<J>(r, j);
         }
     }
-#pragma unroll
-    for (int j = -J; j <= -1; ++j) add_tap(p + j, vb[-j - 1]);
-    // forward chain: j = 0 .. J+1
-    add_tap(p, a.F[J] * r.e0 * (J == 0 ? r.mlo : 1.0f));
-    add_tap(p + 1, a.F[J + 1] * r.e1 * (J == 0 ? r.mhi : 1.0f));
+    // forward chain state: e_{q-2}, e_{q-1} for the pair starting at q = 2
     float em = r.e0, ec = r.e1;
 #pragma unroll
-    for (int j = 2; j <= J + 1; ++j) {
-        const float en = fmaf(r.af, ec, -(r.bf * em));
-        em = ec;
-        ec = en;
-        float v = a.F[J + j] * en;
-        if (j == J + 1) v *= r.mhi;
-        add_tap(p + j, v);
+    for (int q = P0; q <= J + 2; q += 2) {
+        float lo, hi;
+        if (q <= -2) {
+            lo = q >= -J ? vb[-q - 1] : 0.0f;
+            hi = vb[-q - 2];
+        } else if (q == 0) {
+            lo = a.F[J + 1] * r.e0 * tap_mask<J>(r, 0);
+            hi = a.F[J + 2] * r.e1 * tap_mask<J>(r, 1);
+        } else {
+            const float e_lo = fmaf(r.af, ec, -(r.bf * em));
+            lo = a.F[J + 1 + q] * e_lo * tap_mask<J>(r, q);
+            hi = 0.0f;
+            if (q + 1 <= J + 2) {
+                const float e_hi = fmaf(r.af, e_lo, -(r.bf * ec));
+                hi = a.F[J + 2 + q] * e_hi * tap_mask<J>(r, q + 1);
+                em = e_lo;
+                ec = e_hi;
+            }
+        }
+        add_pair(p + q / 2, lo, hi);
     }
 }
 
 template <bool STATIC, int J>
 __global__ void __launch_bounds__(RF_THREADS) rf_synth_kernel(const RfArgs a) {
-    extern __shared__ float sh[];  // [RF_PAD + T + RF_PAD]
+    constexpr int PAD = rf_pad(J);
+    extern __shared__ float sh[];  // [PAD + T + PAD]
     __shared__ int claim[64];
-    __shared__ int nbw[32];   // nb of each lower-half winner, by residue
-    float* tr = sh + RF_PAD;
+    __shared__ int nbw[32];   // pair index of each lower-half winner, by residue
+    float* tr = sh + PAD;
     const int e = blockIdx.x;
     const int f = STATIC ? 0 : blockIdx.y;
     const int an = blockIdx.z;
     const int l = threadIdx.x;
-    for (int i = l; i < a.T + 2 * RF_PAD; i += RF_THREADS) sh[i] = 0.0f;
+    for (int i = l; i < a.T + 2 * PAD; i += RF_THREADS) sh[i] = 0.0f;
     claim[l] = -1;
     __syncthreads();
 
@@ -186,17 +223,17 @@ __global__ void __launch_bounds__(RF_THREADS) rf_synth_kernel(const RfArgs a) {
             if (!more) break;
             continue;
         }
-        // claim: one winner per residue of nb modulo 32 in each half of the wave
-        const int slot = (r.nb & 31) | (l & 32);
+        // claim: one winner per residue of the pair index modulo 32 in each half of the wave
+        const int slot = (r.nbp & 31) | (l & 32);
         const int ep = epoch & 0x1ffffff;   // a stale tag can only make a lane yield
         const int tag = (ep << 6) | l;
         if (has) claim[slot] = tag;
         __builtin_amdgcn_wave_barrier();
         bool win = has && claim[slot] == tag;
-        if (win && l < 32) nbw[slot] = r.nb;
+        if (win && l < 32) nbw[slot] = r.nbp;
         __builtin_amdgcn_wave_barrier();
-        // same nb won in both halves: the upper half yields
-        if (win && l >= 32 && (claim[slot & 31] >> 6) == ep && nbw[slot & 31] == r.nb) win = false;
+        // same pair won in both halves: the upper half yields
+        if (win && l >= 32 && (claim[slot & 31] >> 6) == ep && nbw[slot & 31] == r.nbp) win = false;
         __builtin_amdgcn_wave_barrier();
         if (win) {
             emit<J>(a, tr, r);
@@ -243,7 +280,7 @@ extern "C" int rf_synth(const fq_probe* probe, const fq_tx* tx, const fq_pulse* 
     FQ_REQUIRE(n_scat >= 0, "n_scat must be >= 0");
     FQ_REQUIRE(rf != nullptr && aligned16(rf), "rf must be a 16-byte aligned device pointer");
     FQ_REQUIRE(n_scat == 0 || (pos && amp), "pos/amp must not be NULL");
-    FQ_REQUIRE(n_samples + 2 * RF_PAD <= RF_LDS_FLOATS, "n_samples too large");
+    FQ_REQUIRE(n_samples + 2 * RF_MAX_PAD <= RF_LDS_FLOATS, "n_samples too large");
     const int E = probe->nx_el * probe->ny_el;
     const int A = tx->n_angles;
     hipStream_t s = as_stream(stream);
@@ -253,7 +290,7 @@ extern "C" int rf_synth(const fq_probe* probe, const fq_tx* tx, const fq_pulse* 
     const double sig = pulse->n_cycles / (2.0 * std::sqrt(2.0 * std::log(2.0)) * probe->fc_hz) * probe->fs_hz;
     const double half = pulse->trunc_sigmas * sig;
     const int J = (int)std::floor(half);
-    FQ_REQUIRE(J <= RF_MAX_J, "pulse longer than %d samples", 2 * RF_MAX_J + 2);
+    FQ_REQUIRE(J <= RF_MAX_J, "pulse longer than %d samples", 2 * RF_MAX_J + 3);
     TxHost th = make_tx(*probe, *tx);
     RfArgs a{};
     a.pos = pos;
@@ -274,7 +311,7 @@ extern "C" int rf_synth(const fq_probe* probe, const fq_tx* tx, const fq_pulse* 
     a.nu = (float)(probe->fc_hz / probe->fs_hz);
     a.two_cos_theta = (float)(2.0 * std::cos(2.0 * M_PI * probe->fc_hz / probe->fs_hz));
     a.r_ref = (float)pulse->r_ref_m;
-    for (int j = -J; j <= J + 1; ++j) a.F[J + j] = (float)std::exp(-(double)j * j / (2.0 * sig * sig));
+    for (int j = -J - 1; j <= J + 3; ++j) a.F[J + 1 + j] = (float)std::exp(-(double)j * j / (2.0 * sig * sig));
     for (int i = 0; i < A; ++i) {
         a.ux[i] = th.ux[i];
         a.uy[i] = th.uy[i];
@@ -283,7 +320,7 @@ extern "C" int rf_synth(const fq_probe* probe, const fq_tx* tx, const fq_pulse* 
     }
     const RfFn fn = rf_fn_j<0>(pos_static != 0, J);
     FQ_REQUIRE(fn != nullptr, "no kernel for a pulse half-support of %d samples", J);
-    const size_t lds = sizeof(float) * (size_t)(n_samples + 2 * RF_PAD);
+    const size_t lds = sizeof(float) * (size_t)(n_samples + 2 * rf_pad(J));
     hipLaunchKernelGGL(fn, dim3(E, pos_static ? 1 : n_frames, A), dim3(RF_THREADS), lds, s, a);
     FQ_LAUNCH_CHECK();
     return FQ_OK;
