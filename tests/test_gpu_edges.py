@@ -102,3 +102,30 @@ def test_invalid_workspace_is_reported(gpu):
     with pytest.raises(gpu.FqError) as e:
         gpu.das_beamform(probe, tx, grid, rf, iq, ws)
     assert e.value.status == 2
+
+
+@pytest.mark.parametrize('n_cycles,trunc', [(2.0, 5.0), (2.0, 3.0), (1.0, 2.0), (1.0, 1.2), (0.5, 1.0),
+                                            (0.5, 1.5), (4.0, 4.5), (4.0, 4.6)])
+def test_rf_synth_pulse_lengths(gpu, n_cycles, trunc):
+    """Pulse half-widths J = floor(trunc * sigma) of both parities, from 0 to the largest
+    supported (17, 10, 3, 2, 0, 1, 30, 31 samples at fc / fs = 7.8 / 31.25 MHz): the taps
+    are added in pairs of samples whose first pair start and edge-tap masks depend on J.
+    Scatterers cover the whole record and beyond both ends, over two moving frames."""
+    import torch
+    import paper_2509_05464_amd as fq
+    acq = C1.with_(n_frames=2)
+    probe, tx, grid, _ = structs(acq)
+    pulse = fq.make_pulse(n_cycles, trunc, 1e-3)
+    rng = np.random.default_rng(int(10 * n_cycles + 100 * trunc))
+    S = 300
+    z_end = acq.n_samples * acq.c / acq.fs / 2
+    pos = np.stack([rng.uniform(-3e-3, 3e-3, (2, S)), rng.uniform(-3e-3, 3e-3, (2, S)),
+                    rng.uniform(0.02e-3, 1.03 * z_end, (2, S))], axis=2).astype(np.float32)
+    amp = rng.standard_normal(S).astype(np.float32)
+    rf = torch.empty((2, acq.n_angles, acq.n_elem, acq.n_samples), dtype=torch.float32, device='cuda')
+    gpu.rf_synth(probe, tx, pulse, dev(pos), dev(amp), rf, pos_static=False)
+    sel = native.all_traces(2, acq.n_angles, acq.n_elem)
+    want = native.rf_traces(acq, pos, amp, sel, dict(n_cycles=n_cycles, trunc_sigmas=trunc, r_ref=1e-3))
+    err = rel_l2(rf.cpu().numpy().reshape(sel.shape[0], -1), want)
+    print('pulse', n_cycles, trunc, 'rf rel L2', err)
+    assert err < 2e-5
