@@ -506,7 +506,8 @@ def main():
         'stage_ms': stage_ms,
         'filter_streams': 1 if args.serial else 3,
         'das_gunits_per_s': units / t_das / 1e9,
-        'pd_volumes_per_s': {
+        'pd_volumes_per_s': None,   # each path timed alone, set below
+        'pd_volumes_per_s_in_step': {
             'svd_fp32': 1e3 / (stage_ms['gram_fp32'] + stage_ms['svd_fp32']),
             'svd_split4_bf16': 1e3 / (stage_ms['gram_split_bf16'] + stage_ms['svd_split_bf16']),
             'learned': 1e3 / stage_ms['lcf_infer'],
@@ -546,6 +547,23 @@ def main():
         b.record()
         torch.cuda.synchronize()
         return a.elapsed_time(b) / reps
+
+    # PD volumes/s of each clutter-filter path on its own (one stream, nothing beside it):
+    # ensemble IQ in HBM -> PD volume; in the step the three paths share the GPU
+    _log('[bench] PD paths alone')
+    alone_ms = {
+        'svd_fp32': timed(lambda: (fq.casorati_gram(iq, G, gws, fq.GRAM_FP32),
+                                   fq.svd_clutter_filter(iq, G, sws, sigma, k1, cfg.cutoff, pd=pd_svd, status=st1))),
+        'svd_split4_bf16': timed(lambda: (fq.casorati_gram(iq, G2, gws2, fq.GRAM_SPLIT4_BF16),
+                                          fq.svd_clutter_filter(iq, G2, sws2, sigma2, k2, cfg.cutoff, pd=pd_split,
+                                                                status=st2))),
+        'learned': timed(lambda: filt.infer(iq, pd_lcf)),
+    }
+    out['pd_volumes_per_s'] = {k: 1e3 / v for k, v in alone_ms.items()}
+    out['pd_volumes_per_s_note'] = ('each path timed alone on one stream (mean of 5 after a warm-up): Gram + '
+                                    'eigendecomposition + cutoff + fused projection and PD, or learned inference '
+                                    'with PD; pd_volumes_per_s_in_step: the same stages inside the step, beside '
+                                    'the other two filters')
 
     ssm_ms = timed(lambda: fq.spatial_similarity(iq, vecs, M, ssm_ws, C_ssm, k_ssm))
     svd_ssm_ms = timed(lambda: fq.svd_clutter_filter(iq, G, sws, sigma3, k3, fq.CUTOFF_SSM, pd=pd_ssm, status=st3))
