@@ -177,7 +177,7 @@ struct QlArgs {
 
 __global__ void __launch_bounds__(64) ql_kernel(const QlArgs a) {
     __shared__ double d[FQ_MAX_NT], e[FQ_MAX_NT];
-    __shared__ int s_bad;
+    __shared__ double s_sc;
     const int n = a.n, l0 = threadIdx.x;
     for (int i = l0; i < n; i += 64) {
         d[i] = a.d[i];
@@ -194,27 +194,40 @@ __global__ void __launch_bounds__(64) ql_kernel(const QlArgs a) {
             e[i] *= isc;
         }
         e[n - 1] = 0.0;
-        const double eps = 2.220446049250313e-16;
-        int cnt = 0, bad = 0;
-        for (int l = 0; l < n && !bad; ++l) {
-            for (int it = 0;; ++it) {
-                int m = l;
-                for (; m < n - 1; ++m) {
-                    const double dd = fabs(d[m]) + fabs(d[m + 1]);
-                    if (fabs(e[m]) <= eps * dd) break;
-                }
-                if (m == l) break;
-                if (it >= QL_MAX_ITER || cnt + (m - l) > a.cap) {
-                    bad = 1;
+        s_sc = sc;
+    }
+    __syncthreads();
+    const double eps = 2.220446049250313e-16;
+    // The wave runs the iteration in lockstep: the search for the deflation point is
+    // wave-parallel, each sweep of rotations runs on lane 0 (a dependent chain).
+    int cnt = 0, bad = 0;
+    for (int l = 0; l < n && !bad; ++l) {
+        for (int it = 0;; ++it) {
+            // m = the first index >= l with a negligible off-diagonal e[m], n - 1 if none
+            int m = n - 1;
+            for (int m0 = l; m0 < n - 1; m0 += 64) {
+                const int mm = m0 + l0;
+                bool small = false;
+                if (mm < n - 1) small = fabs(e[mm]) <= eps * (fabs(d[mm]) + fabs(d[mm + 1]));
+                const uint64_t b = __ballot(small);
+                if (b) {
+                    m = m0 + __ffsll((unsigned long long)b) - 1;
                     break;
                 }
+            }
+            if (m == l) break;
+            if (it >= QL_MAX_ITER || cnt + (m - l) > a.cap) {
+                bad = 1;
+                break;
+            }
+            int split = 0;
+            if (l0 == 0) {
                 // Wilkinson shift from the leading 2x2 block
                 double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
                 double r = sqrt(g * g + 1.0);
                 g = d[m] - d[l] + e[l] / (g + (g >= 0.0 ? r : -r));
                 double s = 1.0, c = 1.0, p = 0.0;
                 int i = m - 1;
-                bool split = false;
                 // d[i], d[i+1], e[i] of the current plane; the next plane's e and d are
                 // read one step ahead (this step writes only e[i+1] and d[i+1])
                 double ei = e[i], di = d[i], dip1 = d[i + 1];
@@ -227,7 +240,7 @@ __global__ void __launch_bounds__(64) ql_kernel(const QlArgs a) {
                         e[i + 1] = 0.0;
                         d[i + 1] = dip1 - p;
                         e[m] = 0.0;
-                        split = true;
+                        split = 1;
                         break;
                     }
                     // 1/sqrt(x) from the hardware estimate and two Newton steps
@@ -250,15 +263,20 @@ __global__ void __launch_bounds__(64) ql_kernel(const QlArgs a) {
                     dip1 = di;
                     di = d_nx;
                 }
-                if (split) continue;
-                d[l] -= p;
-                e[l] = g;
-                e[m] = 0.0;
+                if (!split) {
+                    d[l] -= p;
+                    e[l] = g;
+                    e[m] = 0.0;
+                }
             }
+            cnt = __shfl(cnt, 0);
+            __syncthreads();   // lane 0's updates of d and e before the next search
         }
+    }
+    if (l0 == 0) {
+        const double sc = s_sc;
         for (int i = 0; i < n; ++i) d[i] *= sc;
         *a.rot_n = cnt;
-        s_bad = bad;
         if (a.status) *a.status = bad ? FQ_E_NUMERIC : FQ_OK;
     }
     __syncthreads();
