@@ -494,6 +494,10 @@ struct PdArgs {
     float inv_nt;
 };
 
+// The V_K copy (vk) is zero beyond column K, so every instantiation runs all KM columns
+// without a per-column test: the extra terms add exact zeros for finite data (a voxel
+// with a non-finite sample has a non-finite PD either way).  Frames are unrolled by 4 so
+// that several HBM loads of a voxel's series are in flight.
 template <int KM>
 __global__ void __launch_bounds__(256) project_pd_kernel(const PdArgs a) {
     const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -504,30 +508,28 @@ __global__ void __launch_bounds__(256) project_pd_kernel(const PdArgs a) {
 #pragma unroll
     for (int k = 0; k < KM; ++k) p[k] = make_float2(0.f, 0.f);
     if (K > 0) {
+#pragma unroll 4
         for (int f = 0; f < a.nt; ++f) {
             const float2 s = a.iq[(int64_t)f * a.nv + v];
             const float2* vr = a.vk + f * KMAX;
 #pragma unroll
             for (int k = 0; k < KM; ++k) {
-                if (k < K) {
-                    const float2 w = vr[k];
-                    p[k].x = fmaf(s.x, w.x, fmaf(-s.y, w.y, p[k].x));
-                    p[k].y = fmaf(s.x, w.y, fmaf(s.y, w.x, p[k].y));
-                }
+                const float2 w = vr[k];
+                p[k].x = fmaf(s.x, w.x, fmaf(-s.y, w.y, p[k].x));
+                p[k].y = fmaf(s.x, w.y, fmaf(s.y, w.x, p[k].y));
             }
         }
     }
     float acc = 0.f;
+#pragma unroll 4
     for (int f = 0; f < a.nt; ++f) {
         float2 r = a.iq[(int64_t)f * a.nv + v];
         const float2* vr = a.vk + f * KMAX;
 #pragma unroll
         for (int k = 0; k < KM; ++k) {
-            if (k < K) {
-                const float2 w = vr[k];   // subtract p_k conj(w)
-                r.x -= p[k].x * w.x + p[k].y * w.y;
-                r.y -= p[k].y * w.x - p[k].x * w.y;
-            }
+            const float2 w = vr[k];   // subtract p_k conj(w)
+            r.x -= p[k].x * w.x + p[k].y * w.y;
+            r.y -= p[k].y * w.x - p[k].x * w.y;
         }
         if (a.out) a.out[(int64_t)f * a.nv + v] = r;
         acc = fmaf(r.x, r.x, fmaf(r.y, r.y, acc));
