@@ -34,17 +34,18 @@ def test_rf_synth_full_size_sampled_traces(gpu):
     assert err < 2e-5
 
 
-def test_das_full_size_sampled_voxels(gpu):
-    print('c2 das', flush=True)
+@pytest.mark.parametrize('interp', [0, 1])
+def test_das_full_size_sampled_voxels(gpu, interp):
+    print('c2 das interp', interp, flush=True)
     rng = np.random.default_rng(2)
     rf = rng.standard_normal((ACQ.n_frames, ACQ.n_angles, ACQ.n_elem, ACQ.n_samples), dtype=np.float32)
-    iq = gpu_das(ACQ, dev(rf), 0)
+    iq = gpu_das(ACQ, dev(rf), interp)
     # voxels at the corners, the tile edges and random positions
     corners = [0, ACQ.nx - 1, ACQ.n_vox - 1, ACQ.nx * ACQ.ny * (ACQ.nz - 1), 15 + ACQ.nx * 16 + ACQ.nx * ACQ.ny * 3]
     vox = np.concatenate([corners, rng.integers(0, ACQ.n_vox, 27)]).astype(np.int64)
     got = iq[:, torch_index(vox)].cpu().numpy()
     del iq
-    want = native.das_from_rf(ACQ, rf, vox, 0)
+    want = native.das_from_rf(ACQ, rf, vox, interp)
     err = rel_l2(got, want)
     print('c2 das rel L2', err)
     assert err < 1e-4
