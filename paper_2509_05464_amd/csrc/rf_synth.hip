@@ -1,5 +1,11 @@
 // rf_synth: analytic RF of point scatterers under tilted plane-wave transmits (gfx950).
 //
+// Two forms.  The direct form (this header) adds every pulse sample of every scatterer;
+// it serves pulses cut below 5 sigma or narrower than ~3.3 samples.  The spreading form
+// (further down) serves the others, the workloads' 2-cycle pulse among them: the pulse
+// envelope is split into two Gaussians, scatterers are spread onto a half-rate complex
+// trace with the narrow one, and the trace is filtered with the other.
+//
 // One workgroup is one wavefront and owns one trace (frame, transmit, receive element)
 // held in LDS, with a zero guard band on both sides so that pulse taps falling off the
 // record need no bounds test.  Each lane takes a scatterer, computes its two-way delay
@@ -251,6 +257,204 @@ __global__ void __launch_bounds__(RF_THREADS) rf_synth_kernel(const RfArgs a) {
     }
 }
 
+
+// ---------------------------------------------------------------- spreading form
+//
+// For a pulse kept to at least 5 sigma (the tail it drops is below 3.7e-6 of the peak)
+// and at least ~3.3 samples wide, the trace is formed without evaluating the pulse at
+// every sample.  The pulse is the real part of a carrier times a Gaussian envelope,
+//   A g(n - x) = Re[ e^{i theta n} c env(n - x) ],  c = A e^{-i theta x},
+// and the envelope, of variance s^2, is the convolution of two Gaussians of variance
+// s^2 / 2 each (phi and psi).  Each scatterer therefore adds c phi(2m - x) to a complex
+// trace on every other sample (index m, sample 2m): NT taps around x / 2, with phi
+// evaluated by the same split as above (a lane-independent factor F_j times a geometric
+// sequence, here complex: one complex multiply by a real ratio and two FMAs per tap).
+// After all scatterers, each output sample is
+//   rf[n] = Re[ e^{i theta n} sum_m psi(n - 2m) B[m] ],
+// psi including the factor 2 of the half-rate grid and the Gaussian normalisation.
+// Errors against the pulse cut at 5 sigma: the dropped tail (< 3.7e-6 of each pulse
+// peak), aliasing of the half-rate grid exp(-pi^2 s^2 / 8) (6e-7 at s = 3.4 samples),
+// and the cut ends of phi (taps to |2j - f| >= sqrt(24) sigma_phi) and psi (17 natural
+// log units).  The claim scheme is the one of the direct form, on the half-rate index:
+// one complex sample (8 bytes) per tap.
+constexpr int SP_MAX_NT = 32;      // taps (even)
+constexpr int SP_MAX_P = 48;       // half-width of psi, samples
+
+struct SpArgs {
+    const float* pos;
+    const float* amp;
+    float* rf;
+    int64_t n_scat;
+    int n_frames, n_angles, n_elem, T;
+    int nx_el;
+    int accumulate;
+    int J;                  // acceptance: x in (-(J+2), T+J+1), as the direct form
+    int guard;              // half-rate guard band (complex words) on each side
+    int P;                  // psi half-width
+    double pitch_x, pitch_y;
+    double fs_c;            // fs / c
+    double nu;              // fc / fs
+    float kphi;             // -log2(e) / (2 sigma_phi^2)
+    float r_ref;
+    float F[SP_MAX_NT];     // F[j - j0] = exp(-2 j^2 / sigma_phi^2)
+    float psiT[2 * SP_MAX_P + 2];   // psiT[t + P + 1], t = -P-1 .. P (psiT[0] = 0)
+    double ux[FQ_MAX_ANGLES], uy[FQ_MAX_ANGLES], uz[FQ_MAX_ANGLES], t0s[FQ_MAX_ANGLES];
+};
+
+struct SpRec {
+    int mb;            // half-rate index of tap 0
+    float rr, ri;      // c phi(-f) / F_0 ... : value of tap 0 before F_0
+    float rho, rhoi;   // ratio of consecutive taps and its inverse
+};
+
+template <int NT>
+__device__ __forceinline__ bool make_sp(const SpArgs& a, const float* posf, int64_t s, double pex, double pey,
+                                        double ux, double uy, double uz, double t0s, SpRec& r) {
+    const double px = posf[3 * s], py = posf[3 * s + 1], pz = posf[3 * s + 2];
+    const double dx = px - pex, dy = py - pey;
+    const double rho = sqrt_nr(dx * dx + dy * dy + pz * pz);
+    const double x = (ux * px + uy * py + uz * pz) * a.fs_c - t0s + rho * a.fs_c;
+    if (!(x > -(double)(a.J + 2) && x < (double)(a.T + a.J + 1))) return false;   // also rejects NaN
+    const double fl = floor(0.5 * x);
+    r.mb = (int)fl;
+    const float f = (float)(x - 2.0 * fl);   // in [0, 2)
+    const float2 c = cis_cycles(-x * a.nu);   // e^{-i theta x}
+    const float scale = a.amp[s] * a.r_ref * __builtin_amdgcn_rcpf((float)rho);
+    // phi(2j - f) = F_j rho^j G, G = exp(-f^2 / (2 sigma_phi^2)), rho = exp(2 f / sigma_phi^2);
+    // exponent arguments are bounded by 4 / sigma_phi^2: the bare hardware exp2 is enough
+    const float g = scale * __builtin_amdgcn_exp2f(a.kphi * f * f);
+    r.rho = __builtin_amdgcn_exp2f(-4.0f * a.kphi * f);
+    r.rhoi = __builtin_amdgcn_exp2f(4.0f * a.kphi * f);
+    r.rr = g * c.x;
+    r.ri = g * c.y;
+    return true;
+}
+
+__device__ __forceinline__ void add_c(float2* p, float re, float im) {
+    float2 v = *p;
+    v.x += re;
+    v.y += im;
+    *p = v;
+    __builtin_amdgcn_wave_barrier();
+}
+
+template <int NT>
+__device__ __forceinline__ void emit_sp(const SpArgs& a, float2* tr, const SpRec& r) {
+    constexpr int J0 = -NT / 2 + 1;
+    float2* p = tr + r.mb;
+    float br[-J0 > 0 ? -J0 : 1], bi[-J0 > 0 ? -J0 : 1];
+    {
+        float vr = r.rr, vi = r.ri;
+#pragma unroll
+        for (int j = -1; j >= J0; --j) {
+            vr *= r.rhoi;
+            vi *= r.rhoi;
+            br[-j - 1] = a.F[j - J0] * vr;
+            bi[-j - 1] = a.F[j - J0] * vi;
+        }
+    }
+#pragma unroll
+    for (int j = J0; j <= -1; ++j) add_c(p + j, br[-j - 1], bi[-j - 1]);
+    float vr = r.rr, vi = r.ri;
+#pragma unroll
+    for (int j = 0; j < NT + J0; ++j) {
+        if (j > 0) {
+            vr *= r.rho;
+            vi *= r.rho;
+        }
+        add_c(p + j, a.F[j - J0] * vr, a.F[j - J0] * vi);
+    }
+}
+
+template <bool STATIC, int NT>
+__global__ void __launch_bounds__(RF_THREADS) rf_spread_kernel(const SpArgs a) {
+    extern __shared__ float2 shc[];   // [guard + (T+1)/2 + guard] complex
+    __shared__ int claim[64];
+    __shared__ int nbw[32];
+    const int M = (a.T + 1) / 2 + 2 * a.guard;
+    float2* tr = shc + a.guard;
+    const int e = blockIdx.x;
+    const int f = STATIC ? 0 : blockIdx.y;
+    const int an = blockIdx.z;
+    const int l = threadIdx.x;
+    for (int i = l; i < M; i += RF_THREADS) shc[i] = make_float2(0.0f, 0.0f);
+    claim[l] = -1;
+    __syncthreads();
+
+    const double pex = ((e % a.nx_el) - 0.5 * (a.nx_el - 1)) * a.pitch_x;
+    const double pey = ((e / a.nx_el) - 0.5 * ((a.n_elem / a.nx_el) - 1)) * a.pitch_y;
+    const float* posf = a.pos + (STATIC ? 0 : (int64_t)f * a.n_scat * 3);
+    const double ux = a.ux[an], uy = a.uy[an], uz = a.uz[an], t0s = a.t0s[an];
+    const uint64_t below = (l == 0) ? 0ull : (~0ull >> (64 - l));
+
+    bool has = false;
+    SpRec r{};
+    int64_t next = 0;
+    for (int epoch = 1;; ++epoch) {
+        const uint64_t need = __ballot(!has);
+        if (!has) {
+            const int64_t s = next + __popcll(need & below);
+            if (s < a.n_scat) has = make_sp<NT>(a, posf, s, pex, pey, ux, uy, uz, t0s, r);
+        }
+        next += __popcll(need);
+        const bool more = next < a.n_scat;
+        if (!__ballot(has)) {
+            if (!more) break;
+            continue;
+        }
+        const int slot = (r.mb & 31) | (l & 32);
+        const int ep = epoch & 0x1ffffff;   // a stale tag can only make a lane yield
+        const int tag = (ep << 6) | l;
+        if (has) claim[slot] = tag;
+        __builtin_amdgcn_wave_barrier();
+        bool win = has && claim[slot] == tag;
+        if (win && l < 32) nbw[slot] = r.mb;
+        __builtin_amdgcn_wave_barrier();
+        if (win && l >= 32 && (claim[slot & 31] >> 6) == ep && nbw[slot & 31] == r.mb) win = false;
+        __builtin_amdgcn_wave_barrier();
+        if (win) {
+            emit_sp<NT>(a, tr, r);
+            has = false;
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+    __syncthreads();
+
+    // rf[n] = Re[e^{i theta n} sum_m psi(n - 2m) B[m]], m = mlo .. mlo + P
+    const int P = a.P;
+    const int nf = STATIC ? a.n_frames : 1;
+    for (int n = l; n < a.T; n += RF_THREADS) {
+        const int mlo = (n - P + 1) >> 1;   // first m with n - 2m <= P
+        const int odd = (n - P) & 1;        // n - 2 mlo = P - odd
+        float br = 0.0f, bi = 0.0f;
+        for (int k = 0; k <= P; ++k) {
+            const float cf = odd ? a.psiT[2 * P - 2 * k] : a.psiT[2 * P + 1 - 2 * k];
+            const float2 b = tr[mlo + k];
+            br = fmaf(cf, b.x, br);
+            bi = fmaf(cf, b.y, bi);
+        }
+        const float2 cs = cis_cycles((double)n * a.nu);
+        const float v = cs.x * br - cs.y * bi;
+        for (int ff = 0; ff < nf; ++ff) {
+            const int fo = STATIC ? ff : f;
+            float* dst = a.rf + (((int64_t)fo * a.n_angles + an) * a.n_elem + e) * a.T;
+            dst[n] = a.accumulate ? dst[n] + v : v;
+        }
+    }
+}
+
+using SpFn = void (*)(const SpArgs);
+
+template <int NT>
+SpFn sp_fn(bool stat, int nt) {
+    if constexpr (NT > SP_MAX_NT) {
+        return nullptr;
+    } else {
+        if (nt == NT) return stat ? rf_spread_kernel<true, NT> : rf_spread_kernel<false, NT>;
+        return sp_fn<NT + 2>(stat, nt);
+    }
+}
+
 using RfFn = void (*)(const RfArgs);
 
 template <int J>
@@ -290,8 +494,55 @@ extern "C" int rf_synth(const fq_probe* probe, const fq_tx* tx, const fq_pulse* 
     const double sig = pulse->n_cycles / (2.0 * std::sqrt(2.0 * std::log(2.0)) * probe->fc_hz) * probe->fs_hz;
     const double half = pulse->trunc_sigmas * sig;
     const int J = (int)std::floor(half);
-    FQ_REQUIRE(J <= RF_MAX_J, "pulse longer than %d samples", 2 * RF_MAX_J + 3);
     TxHost th = make_tx(*probe, *tx);
+    {
+        // spreading form: pulse kept to >= 5 sigma, half-rate aliasing <= 1.5e-6 (s >= 3.3)
+        const double aphi = 0.5 * sig * sig;   // sigma_phi^2 = sigma_psi^2
+        const int nt = 2 * (int)std::ceil(0.5 * std::sqrt(24.0 * aphi));
+        const int P = (int)std::ceil(std::sqrt(2.0 * aphi * 17.0));
+        if (pulse->trunc_sigmas >= 5.0 && sig >= 3.3 && nt >= 4 && nt <= SP_MAX_NT && P <= SP_MAX_P) {
+            SpArgs a{};
+            a.pos = pos;
+            a.amp = amp;
+            a.rf = rf;
+            a.n_scat = n_scat;
+            a.n_frames = n_frames;
+            a.n_angles = A;
+            a.n_elem = E;
+            a.T = n_samples;
+            a.nx_el = probe->nx_el;
+            a.accumulate = accumulate ? 1 : 0;
+            a.J = J;
+            a.P = P;
+            // taps reach half-rate index floor(x/2) + j, x in (-(J+2), T+J+1), j in [1 - nt/2, nt/2];
+            // psi reads (n - P)/2 .. (n + P)/2 for n in [0, T)
+            a.guard = std::max((J + 4) / 2 + nt / 2, (P + 1) / 2) + 2;
+            a.pitch_x = probe->pitch_x;
+            a.pitch_y = probe->pitch_y;
+            a.fs_c = probe->fs_hz / probe->c_mps;
+            a.nu = probe->fc_hz / probe->fs_hz;
+            a.kphi = (float)(-1.0 / (2.0 * aphi) / std::log(2.0));
+            a.r_ref = (float)pulse->r_ref_m;
+            const int j0 = 1 - nt / 2;
+            for (int j = j0; j < j0 + nt; ++j) a.F[j - j0] = (float)std::exp(-2.0 * (double)j * j / aphi);
+            const double norm = 2.0 / std::sqrt(2.0 * M_PI * aphi * aphi / (sig * sig));
+            a.psiT[0] = 0.0f;
+            for (int t = -P; t <= P; ++t) a.psiT[t + P + 1] = (float)(norm * std::exp(-(double)t * t / (2.0 * aphi)));
+            for (int i = 0; i < A; ++i) {
+                a.ux[i] = th.ux[i];
+                a.uy[i] = th.uy[i];
+                a.uz[i] = th.uz[i];
+                a.t0s[i] = th.t0[i] * probe->fs_hz;
+            }
+            const SpFn fn = sp_fn<4>(pos_static != 0, nt);
+            FQ_REQUIRE(fn != nullptr, "no spreading kernel for %d taps", nt);
+            const size_t lds = sizeof(float2) * (size_t)((n_samples + 1) / 2 + 2 * a.guard);
+            hipLaunchKernelGGL(fn, dim3(E, pos_static ? 1 : n_frames, A), dim3(RF_THREADS), lds, s, a);
+            FQ_LAUNCH_CHECK();
+            return FQ_OK;
+        }
+    }
+    FQ_REQUIRE(J <= RF_MAX_J, "pulse longer than %d samples", 2 * RF_MAX_J + 3);
     RfArgs a{};
     a.pos = pos;
     a.amp = amp;

@@ -107,14 +107,17 @@ def test_invalid_arguments_return_status(lib):
     probe = fq.make_probe(4, 4, 3e-4, 3e-4, 7.8e6, 31.25e6, 1540.0)
     tx = fq.make_tx([(0.0, 0.0)])
     pulse = fq.make_pulse()
-    # RF synthesis: a pulse longer than the compiled tap windows (half-width 8 sigma of a
-    # 5-cycle pulse: 68 samples > 31) and a record longer than 8192 samples; the device
-    # pointers are placeholders that are never dereferenced on these paths
+    # RF synthesis: pulses neither form takes (a 5-cycle pulse cut at 4.9 sigma: direct form,
+    # half-width 41 samples > 31; an 8-cycle pulse kept to 5 sigma: 48 half-rate taps, more
+    # than the spreading form's 32, so it falls back to the direct form, half-width 68) and a
+    # record longer than 8192 samples; the device pointers are placeholders that are never
+    # dereferenced on these paths
     fake = ctypes.c_void_p(1 << 20)
-    long_pulse = fq.make_pulse(5.0, 8.0, 1e-3)
-    st = L.rf_synth(ctypes.byref(probe), ctypes.byref(tx), ctypes.byref(long_pulse), 1, 1, fake, 1, fake, 256, 0,
-                    fake, None)
-    assert st == 1 and b'pulse longer' in L.fq_last_error()
+    for n_cyc, trunc in ((5.0, 4.9), (8.0, 5.0)):
+        long_pulse = fq.make_pulse(n_cyc, trunc, 1e-3)
+        st = L.rf_synth(ctypes.byref(probe), ctypes.byref(tx), ctypes.byref(long_pulse), 1, 1, fake, 1, fake, 256,
+                        0, fake, None)
+        assert st == 1 and b'pulse longer' in L.fq_last_error()
     st = L.rf_synth(ctypes.byref(probe), ctypes.byref(tx), ctypes.byref(pulse), 1, 1, fake, 1, fake, 9000, 0,
                     fake, None)
     assert st == 1 and b'n_samples' in L.fq_last_error()

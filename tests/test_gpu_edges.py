@@ -105,12 +105,15 @@ def test_invalid_workspace_is_reported(gpu):
 
 
 @pytest.mark.parametrize('n_cycles,trunc', [(2.0, 5.0), (2.0, 3.0), (1.0, 2.0), (1.0, 1.2), (0.5, 1.0),
-                                            (0.5, 1.5), (4.0, 4.5), (4.0, 4.6)])
+                                            (0.5, 1.5), (4.0, 4.5), (4.0, 4.6), (3.0, 5.0), (5.0, 6.0)])
 def test_rf_synth_pulse_lengths(gpu, n_cycles, trunc):
-    """Pulse half-widths J = floor(trunc * sigma) of both parities, from 0 to the largest
-    supported (17, 10, 3, 2, 0, 1, 30, 31 samples at fc / fs = 7.8 / 31.25 MHz): the taps
-    are added in pairs of samples whose first pair start and edge-tap masks depend on J.
-    Scatterers cover the whole record and beyond both ends, over two moving frames."""
+    """Both forms of the synthesis at fc / fs = 7.8 / 31.25 MHz.  Direct form (pulse cut
+    below 5 sigma, or narrower than 3.3 samples): half-widths J = floor(trunc * sigma) of
+    both parities from 0 to the largest supported (10, 3, 2, 0, 1, 30, 31 samples), the
+    taps added in pairs of samples whose first pair start and edge-tap masks depend on J.
+    Spreading form (kept to >= 5 sigma, sigma >= 3.3 samples): 12, 18 and 30 half-rate taps
+    (2, 3 and 5 cycles; the last one longer than the direct form supports).  Scatterers
+    cover the whole record and beyond both ends, over two moving frames."""
     import torch
     import paper_2509_05464_amd as fq
     acq = C1.with_(n_frames=2)
