@@ -303,8 +303,8 @@ struct SpArgs {
 
 struct SpRec {
     int mb;            // half-rate index of tap 0
-    float rr, ri;      // c phi(-f) / F_0 ... : value of tap 0 before F_0
-    float rho, rhoi;   // ratio of consecutive taps and its inverse
+    float rr, ri;      // c scale G rho^j0: the first tap (j = j0) before its factor F_j0
+    float rho;         // ratio of consecutive taps
 };
 
 template <int NT>
@@ -321,10 +321,12 @@ __device__ __forceinline__ bool make_sp(const SpArgs& a, const float* posf, int6
     const float2 c = cis_cycles(-x * a.nu);   // e^{-i theta x}
     const float scale = a.amp[s] * a.r_ref * __builtin_amdgcn_rcpf((float)rho);
     // phi(2j - f) = F_j rho^j G, G = exp(-f^2 / (2 sigma_phi^2)), rho = exp(2 f / sigma_phi^2);
-    // exponent arguments are bounded by 4 / sigma_phi^2: the bare hardware exp2 is enough
-    const float g = scale * __builtin_amdgcn_exp2f(a.kphi * f * f);
+    // the taps run forward from j0 = 1 - NT/2, starting at G rho^j0 = exp2(kphi f (f - 4 j0));
+    // the exponents stay within (4 - 8 j0) / (2 sigma_phi^2 ln 2) (~6 for the 2-cycle pulse):
+    // the bare hardware exp2 is enough
+    constexpr int J0 = 1 - NT / 2;
+    const float g = scale * __builtin_amdgcn_exp2f(a.kphi * f * (f - 4.0f * (float)J0));
     r.rho = __builtin_amdgcn_exp2f(-4.0f * a.kphi * f);
-    r.rhoi = __builtin_amdgcn_exp2f(4.0f * a.kphi * f);
     r.rr = g * c.x;
     r.ri = g * c.y;
     return true;
@@ -340,29 +342,16 @@ __device__ __forceinline__ void add_c(float2* p, float re, float im) {
 
 template <int NT>
 __device__ __forceinline__ void emit_sp(const SpArgs& a, float2* tr, const SpRec& r) {
-    constexpr int J0 = -NT / 2 + 1;
-    float2* p = tr + r.mb;
-    float br[-J0 > 0 ? -J0 : 1], bi[-J0 > 0 ? -J0 : 1];
-    {
-        float vr = r.rr, vi = r.ri;
-#pragma unroll
-        for (int j = -1; j >= J0; --j) {
-            vr *= r.rhoi;
-            vi *= r.rhoi;
-            br[-j - 1] = a.F[j - J0] * vr;
-            bi[-j - 1] = a.F[j - J0] * vi;
-        }
-    }
-#pragma unroll
-    for (int j = J0; j <= -1; ++j) add_c(p + j, br[-j - 1], bi[-j - 1]);
+    constexpr int J0 = 1 - NT / 2;
+    float2* p = tr + r.mb + J0;
     float vr = r.rr, vi = r.ri;
 #pragma unroll
-    for (int j = 0; j < NT + J0; ++j) {
-        if (j > 0) {
+    for (int k = 0; k < NT; ++k) {
+        if (k > 0) {
             vr *= r.rho;
             vi *= r.rho;
         }
-        add_c(p + j, a.F[j - J0] * vr, a.F[j - J0] * vi);
+        add_c(p + k, a.F[k] * vr, a.F[k] * vi);
     }
 }
 
