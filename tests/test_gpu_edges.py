@@ -37,14 +37,18 @@ def test_rf_synth_empty_scene(gpu):
     assert float(rf.abs().max()) == 0.0
 
 
-def test_rf_synth_scatterer_at_record_edges(gpu):
-    """Pulses cut by the start and the end of the record (taps outside [0, T) dropped)."""
-    acq = C1.with_(n_frames=1, tilts_deg=((0.0, 0.0),), n_samples=200)
+@pytest.mark.parametrize('T', [200, 201])
+def test_rf_synth_scatterer_at_record_edges(gpu, T):
+    """Pulses cut by the start and the end of the record (taps outside [0, T) dropped), for
+    an even and an odd record length (the half-rate trace of the spreading form holds
+    (T + 1) / 2 samples)."""
+    acq = C1.with_(n_frames=1, tilts_deg=((0.0, 0.0),), n_samples=T)
     probe, tx, grid, pulse = structs(acq)
     z_early = 1.0 * 1540 / 31.25e6 * 5        # arrives ~10 samples after t = 0
     z_late = 1540 / 31.25e6 * 198 / 2          # arrives near the last sample
-    pos = np.array([[[0.0, 0.0, z_early], [0.3e-3, 0.1e-3, z_late]]], np.float32)
-    amp = np.array([1.0, -0.5], np.float32)
+    z_past = 1540 / 31.25e6 * (T + 12) / 2     # arrives after the record: only its leading tail is in
+    pos = np.array([[[0.0, 0.0, z_early], [0.3e-3, 0.1e-3, z_late], [0.0, 0.0, z_past]]], np.float32)
+    amp = np.array([1.0, -0.5, 2.0], np.float32)
     import torch
     rf = torch.empty((1, 1, acq.n_elem, acq.n_samples), dtype=torch.float32, device='cuda')
     gpu.rf_synth(probe, tx, pulse, dev(pos), dev(amp), rf)
