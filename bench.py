@@ -44,9 +44,12 @@ def rf_work(acq, n_scat: int, moving: bool = True) -> dict:
     two FMAs with the Gaussian factor, two adds into the trace); per trace T outputs of the
     interpolation filter, P + 1 complex-by-real MACs (4 FLOP) and the carrier (4 FLOP)."""
     sig = 2.0 / (2.0 * np.sqrt(2.0 * np.log(2.0)) * acq.fc) * acq.fs
-    aphi = 0.5 * sig * sig
+    s2 = sig * sig
+    q = 4.0 * 2.614 / s2
+    alpha = max(1.0 / 3.0, 0.5 * (1.0 - np.sqrt(1.0 - q))) if q < 1.0 else 0.5
+    aphi, bpsi = alpha * s2, (1.0 - alpha) * s2
     nt = 2 * int(np.ceil(0.5 * np.sqrt(24.0 * aphi)))
-    P = int(np.ceil(np.sqrt(2.0 * aphi * 17.0)))
+    P = int(np.ceil(np.sqrt(2.0 * bpsi * 17.0)))
     traces = acq.n_elem * acq.n_angles * (acq.n_frames if moving else 1)
     records = float(n_scat) * acq.n_elem * acq.n_angles * acq.n_frames
     flop = records * nt * 6.0 + float(traces) * acq.n_samples * ((P + 1) * 4.0 + 4.0)

@@ -93,10 +93,10 @@ typedef struct {
  *  Two evaluations: a pulse cut at trunc_sigmas < 5, or narrower than s*fs = 3.3 samples,
  *  is summed sample by sample as written above (half-support trunc_sigmas*s*fs below 32
  *  samples).  Otherwise the pulse is kept whole (the part beyond 5 s is below 3.7e-6 of
- *  its peak) and its Gaussian envelope is split into two Gaussians of variance s^2/2: each
- *  scatterer adds complex taps to a half-rate trace, which a fixed Gaussian filter and
- *  the carrier turn into rf; the result is within ~2e-6 (relative L2) of the truncated sum
- *  for the 2-cycle pulse, for s*fs up to ~9 samples.
+ *  its peak) and its Gaussian envelope is split into two Gaussians (variances ~s^2/3 and
+ *  ~2s^2/3): each scatterer adds complex taps to a half-rate trace, which a fixed Gaussian
+ *  filter and the carrier turn into rf; the result is within ~4e-6 (relative L2) of the
+ *  truncated sum for the 2-cycle pulse, for s*fs up to ~9 samples.
  *  Errors: FQ_E_INVALID for null pointers, non-positive sizes, n_samples > 8192, a pulse
  *  of the first kind whose half-support reaches 32 samples.  n_scat == 0 is valid.
  *  The order in which echoes are summed depends on scheduling, so results agree with a

@@ -264,8 +264,8 @@ __global__ void __launch_bounds__(RF_THREADS) rf_synth_kernel(const RfArgs a) {
 // and at least ~3.3 samples wide, the trace is formed without evaluating the pulse at
 // every sample.  The pulse is the real part of a carrier times a Gaussian envelope,
 //   A g(n - x) = Re[ e^{i theta n} c env(n - x) ],  c = A e^{-i theta x},
-// and the envelope, of variance s^2, is the convolution of two Gaussians of variance
-// s^2 / 2 each (phi and psi).  Each scatterer therefore adds c phi(2m - x) to a complex
+// and the envelope, of variance s^2, is the convolution of two Gaussians phi and psi of
+// variances alpha s^2 and (1 - alpha) s^2 (alpha ~1/3: the narrow phi needs few taps).  Each scatterer therefore adds c phi(2m - x) to a complex
 // trace on every other sample (index m, sample 2m): NT taps around x / 2, with phi
 // evaluated by the same split as above (a lane-independent factor F_j times a geometric
 // sequence, here complex: one complex multiply by a real ratio and two FMAs per tap).
@@ -273,9 +273,9 @@ __global__ void __launch_bounds__(RF_THREADS) rf_synth_kernel(const RfArgs a) {
 //   rf[n] = Re[ e^{i theta n} sum_m psi(n - 2m) B[m] ],
 // psi including the factor 2 of the half-rate grid and the Gaussian normalisation.
 // Errors against the pulse cut at 5 sigma: the dropped tail (< 3.7e-6 of each pulse
-// peak), aliasing of the half-rate grid exp(-pi^2 s^2 / 8) (6e-7 at s = 3.4 samples),
-// and the cut ends of phi (taps to |2j - f| >= sqrt(24) sigma_phi) and psi (17 natural
-// log units).  The claim scheme is the one of the direct form, on the half-rate index:
+// peak), aliasing of the half-rate grid 2 exp(-pi^2 alpha (1 - alpha) s^2 / 2) (alpha is
+// chosen on the host to keep it below 5e-6), and the cut ends of phi (taps to
+// |2j - f| >= sqrt(24) sigma_phi) and psi (17 natural log units).  The claim scheme is the one of the direct form, on the half-rate index:
 // one complex sample (8 bytes) per tap.
 constexpr int SP_MAX_NT = 32;      // taps (even)
 constexpr int SP_MAX_P = 48;       // half-width of psi, samples
@@ -485,11 +485,18 @@ extern "C" int rf_synth(const fq_probe* probe, const fq_tx* tx, const fq_pulse* 
     const int J = (int)std::floor(half);
     TxHost th = make_tx(*probe, *tx);
     {
-        // spreading form: pulse kept to >= 5 sigma, half-rate aliasing <= 1.5e-6 (s >= 3.3)
-        const double aphi = 0.5 * sig * sig;   // sigma_phi^2 = sigma_psi^2
+        // spreading form for a pulse kept to >= 5 sigma and at least 3.3 samples wide.  The
+        // split sigma_phi^2 = alpha s^2, sigma_psi^2 = (1 - alpha) s^2 takes the smallest
+        // alpha (fewest taps) whose half-rate aliasing, 2 exp(-pi^2 alpha (1 - alpha) s^2 / 2),
+        // stays below 5e-6: alpha (1 - alpha) s^2 >= 2.614.
+        const double s2 = sig * sig;
+        const double q = 4.0 * 2.614 / s2;
+        // (not below 1/3: a narrower phi would make psi longer than SP_MAX_P for wide pulses)
+        const double alpha = q < 1.0 ? std::max(1.0 / 3.0, 0.5 * (1.0 - std::sqrt(1.0 - q))) : 0.5;
+        const double aphi = alpha * s2, bpsi = s2 - aphi;
         const int nt = 2 * (int)std::ceil(0.5 * std::sqrt(24.0 * aphi));
-        const int P = (int)std::ceil(std::sqrt(2.0 * aphi * 17.0));
-        if (pulse->trunc_sigmas >= 5.0 && sig >= 3.3 && nt >= 4 && nt <= SP_MAX_NT && P <= SP_MAX_P) {
+        const int P = (int)std::ceil(std::sqrt(2.0 * bpsi * 17.0));
+        if (pulse->trunc_sigmas >= 5.0 && sig >= 3.3 && q < 1.0 && nt >= 4 && nt <= SP_MAX_NT && P <= SP_MAX_P) {
             SpArgs a{};
             a.pos = pos;
             a.amp = amp;
@@ -514,9 +521,9 @@ extern "C" int rf_synth(const fq_probe* probe, const fq_tx* tx, const fq_pulse* 
             a.r_ref = (float)pulse->r_ref_m;
             const int j0 = 1 - nt / 2;
             for (int j = j0; j < j0 + nt; ++j) a.F[j - j0] = (float)std::exp(-2.0 * (double)j * j / aphi);
-            const double norm = 2.0 / std::sqrt(2.0 * M_PI * aphi * aphi / (sig * sig));
+            const double norm = 2.0 / std::sqrt(2.0 * M_PI * aphi * bpsi / s2);
             a.psiT[0] = 0.0f;
-            for (int t = -P; t <= P; ++t) a.psiT[t + P + 1] = (float)(norm * std::exp(-(double)t * t / (2.0 * aphi)));
+            for (int t = -P; t <= P; ++t) a.psiT[t + P + 1] = (float)(norm * std::exp(-(double)t * t / (2.0 * bpsi)));
             for (int i = 0; i < A; ++i) {
                 a.ux[i] = th.ux[i];
                 a.uy[i] = th.uy[i];

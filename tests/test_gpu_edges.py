@@ -115,7 +115,7 @@ def test_rf_synth_pulse_lengths(gpu, n_cycles, trunc):
     below 5 sigma, or narrower than 3.3 samples): half-widths J = floor(trunc * sigma) of
     both parities from 0 to the largest supported (10, 3, 2, 0, 1, 30, 31 samples), the
     taps added in pairs of samples whose first pair start and edge-tap masks depend on J.
-    Spreading form (kept to >= 5 sigma, sigma >= 3.3 samples): 12, 18 and 30 half-rate taps
+    Spreading form (kept to >= 5 sigma, sigma >= 3.3 samples): 10, 16 and 26 half-rate taps
     (2, 3 and 5 cycles; the last one longer than the direct form supports).  Scatterers
     cover the whole record and beyond both ends, over two moving frames."""
     import torch
