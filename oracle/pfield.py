@@ -15,9 +15,11 @@ Readings (the appendix gives the form, not the constants):
   positions, split into v_x x v_y sub-elements at the centres of a regular subdivision;
   a sub-element's directivity is sinc(k b_x u_x) sinc(k b_y u_y) with b its half-widths,
   u the direction cosines towards the scatterer and sinc(x) = sin(x) / x (w = 0: D = 1);
-- an element's response is the mean (not the sum) over its sub-elements, so that it does
-  not depend on how finely the element is subdivided (the far-field limit is the
-  element's own directivity);
+- an element's response is the coherent sum over its sub-elements (Eq. 2), and the
+  transmit field sums over every sub-element of the aperture (Eq. 1): an element split
+  into v sub-elements responds about v times as strongly as one of them in the far field.
+  The mean over the sub-elements (a response independent of the subdivision, whose
+  far-field limit is the element's own directivity) is kept as an option (sub_mean);
 - no elevation lens (a matrix array); transmit apodization W (default 1); transmit
   delays of the plane-wave law dtau = (u_a . p_e - min_e u_a . p_e) / c;
 - amplitude (r_ref / r) on both legs; optional attenuation alpha (dB / (cm MHz)), i.e.
@@ -95,8 +97,9 @@ def frequency_samples(n_samples: int, fs: float, fc: float, floor: float, n_cycl
 
 
 def element_response(f: float, pos: np.ndarray, centres: np.ndarray, wx: float, wy: float, vx: int, vy: int,
-                     c: float, r_ref: float, atten: float) -> np.ndarray:
-    """H[e][s]: mean over the sub-elements of element e of (r_ref/r) e^{i k r} D (complex128)."""
+                     c: float, r_ref: float, atten: float, sub_mean: bool = False) -> np.ndarray:
+    """H[e][s]: sum (Eq. 2), or mean if sub_mean, over the sub-elements of element e of
+    (r_ref/r) e^{i k r} D (complex128)."""
     k = 2.0 * math.pi * f / c
     alpha = atten * NEPER_PER_DB * 100.0 * f / 1e6          # nepers per metre
     H = np.zeros((centres.shape[0], pos.shape[0]), dtype=np.complex128)
@@ -111,13 +114,13 @@ def element_response(f: float, pos: np.ndarray, centres: np.ndarray, wx: float, 
             if wy > 0:
                 D *= np.sinc(k * (wy / (2 * vy)) * d[:, :, 1] / r / math.pi)
             H += (r_ref / r) * np.exp((1j * k - alpha) * r) * D
-    return H / (vx * vy)
+    return H / (vx * vy) if sub_mean else H
 
 
 def fd_rf(nx_el: int, ny_el: int, pitch: float, fc: float, fs: float, c: float, tilts_rad, pos: np.ndarray,
           amp: np.ndarray, n_samples: int, elem_w: Tuple[float, float] = (0.0, 0.0), n_sub: Tuple[int, int] = (1, 1),
           atten: float = 0.0, apod: Optional[np.ndarray] = None, r_ref: float = 1e-3, floor: float = 1e-7,
-          n_cycles: float = 2.0) -> np.ndarray:
+          n_cycles: float = 2.0, sub_mean: bool = False) -> np.ndarray:
     """RF [A][E][T] of one frame of scatterers pos [S][3], amp [S] (float64)."""
     centres = element_centres(nx_el, ny_el, pitch, pitch)
     E = centres.shape[0]
@@ -130,7 +133,7 @@ def fd_rf(nx_el: int, ny_el: int, pitch: float, fc: float, fs: float, c: float, 
     pos = np.asarray(pos, dtype=np.float64)
     amp = np.asarray(amp, dtype=np.float64)
     for j, f, w in zip(js, fk, wk):
-        H = element_response(f, pos, centres, elem_w[0], elem_w[1], n_sub[0], n_sub[1], c, r_ref, atten)
+        H = element_response(f, pos, centres, elem_w[0], elem_w[1], n_sub[0], n_sub[1], c, r_ref, atten, sub_mean)
         tx = (W[None, :] * np.exp(1j * 2.0 * math.pi * f * dtau)) @ H       # [A][S] field at each scatterer
         P = (tx * amp[None, :]) @ H.T                                        # [A][E] echo at each element
         rf += 2.0 * np.real(w * P[:, :, None] * np.exp(-2j * math.pi * j * t / N)[None, None, :])

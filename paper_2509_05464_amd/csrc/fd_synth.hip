@@ -2,7 +2,8 @@
 // Eq. 2; the scatterer-block partition and frequency stepping of Algorithm 2).
 //
 // Per frequency sample f_j = j df (k_j = 2 pi f_j / c), with the element response
-//   H_e(s, f) = (1/v) sum over the v sub-elements mu of element e of
+//   H_e(s, f) = sum over the v sub-elements mu of element e (the coherent sub-element
+//               sum of Eq. 2; Eq. 1 sums every transmitting sub-element) of
 //               (r_ref / r) e^{(i k - alpha) r} sinc(k b_x u_x) sinc(k b_y u_y),
 // the field of transmit a at scatterer s and the echo at receive element m are
 //   T_a(s, f) = sum_e W_e e^{i 2 pi f dtau_ae} H_e(s, f),
@@ -57,7 +58,7 @@ struct FdArgs {
     double bx_df_c, by_df_c;   // directivity cycles per step per unit direction cosine (b df / c)
     double alpha_df;        // attenuation nepers per metre per frequency step
     double df;
-    float r_ref, inv_v;
+    float r_ref;
     double ux[AG], uy[AG], t0[AG];   // transmit directions and first-firing offsets (s)
     double inv_c;
     // inverse transform
@@ -133,11 +134,6 @@ __device__ __forceinline__ void elem_resp(const FdArgs& a, double ex, double ey,
                 z = cmul(z, st);
             }
         }
-    }
-#pragma unroll
-    for (int q = 0; q < KC; ++q) {
-        h[q].x *= a.inv_v;
-        h[q].y *= a.inv_v;
     }
 }
 
@@ -478,7 +474,6 @@ extern "C" int fd_synth(const fq_probe* probe, const fq_tx* tx, const fq_pulse* 
     a.by_df_c = 0.5 * fd->elem_width_y / fd->n_sub_y * df / probe->c_mps;
     a.alpha_df = fd->atten_db_cm_mhz / (20.0 * std::log10(std::exp(1.0))) * 100.0 * df / 1e6;
     a.r_ref = (float)pulse->r_ref_m;
-    a.inv_v = 1.0f / (float)(fd->n_sub_x * fd->n_sub_y);
     a.inv_c = 1.0 / probe->c_mps;
     a.T_len = n_samples;
     a.n_angles_total = A;

@@ -61,8 +61,9 @@ def test_reciprocity_with_directivity_and_sub_elements():
 
 
 def test_sub_elements_converge_to_the_element_directivity_in_the_far_field():
-    """Product theorem: in the far field the mean of v sub-elements with directivity
-    sinc(k b/v u) equals one element with sinc(k b u); the residual is the Fresnel term
+    """Product theorem under Eq. 2's coherent sum: in the far field the sum over v
+    sub-elements with directivity sinc(k b/v u) equals v times one element with sinc(k b u)
+    (the mean option equals the element itself); the residual is the Fresnel term
     ~ k w^2 / (8 r) and falls like 1/r."""
     cen = pfield.element_centres(1, 1, PITCH, PITCH)
     f = FC
@@ -71,7 +72,9 @@ def test_sub_elements_converge_to_the_element_directivity_in_the_far_field():
         pos = np.array([[0.3 * r, -0.2 * r, 0.9 * r]])
         h1 = pfield.element_response(f, pos, cen, 0.3e-3, 0.3e-3, 1, 1, C, 1e-3, 0.0)
         h5 = pfield.element_response(f, pos, cen, 0.3e-3, 0.3e-3, 5, 5, C, 1e-3, 0.0)
-        errs.append(abs(h5[0, 0] - h1[0, 0]) / abs(h1[0, 0]))
+        m5 = pfield.element_response(f, pos, cen, 0.3e-3, 0.3e-3, 5, 5, C, 1e-3, 0.0, sub_mean=True)
+        errs.append(abs(h5[0, 0] / 25.0 - h1[0, 0]) / abs(h1[0, 0]))
+        assert abs(m5[0, 0] - h5[0, 0] / 25.0) <= 1e-15 * abs(h5[0, 0])
     k = 2 * math.pi * f / C
     assert errs[0] < k * (0.3e-3) ** 2 / (8 * 1.0) * 2
     assert 3.0 < errs[0] / errs[1] < 5.0
@@ -81,6 +84,30 @@ def test_sub_elements_converge_to_the_element_directivity_in_the_far_field():
     hd = pfield.element_response(f, pos, cen, 0.3e-3, 0.3e-3, 1, 1, C, 1e-3, 0.0)
     x = k * 0.15e-3 * math.sin(math.pi / 4)
     assert abs(abs(hd[0, 0]) / abs(hp[0, 0]) - abs(math.sin(x) / x)) < 1e-12
+
+
+def test_echo_scales_with_the_square_of_the_sub_element_count():
+    """Eq. 1 sums the transmit field over every sub-element and Eq. 2 sums the receive
+    element's sub-elements, so for a scatterer far on axis (where every sub-element sees
+    the same path and directivity 1) splitting each element into v sub-elements scales the
+    echo by v^2 on both legs (here v = 6: 36); the ratio approaches 36 as the Fresnel term
+    k (w/2)^2 / (2 r) vanishes, and the mean option gives a response independent of v."""
+    w = (0.2e-3, 0.2e-3)
+    ratios, ratios_mean = [], []
+    for z in (0.05, 0.2):
+        pos = np.array([[0.0, 0.0, z]])
+        T = 2 * int(z / C * FS) + 64
+        kw = dict(elem_w=w)
+        one = pfield.fd_rf(1, 1, PITCH, FC, FS, C, [(0.0, 0.0)], pos, np.ones(1), T, n_sub=(1, 1), **kw)
+        six = pfield.fd_rf(1, 1, PITCH, FC, FS, C, [(0.0, 0.0)], pos, np.ones(1), T, n_sub=(2, 3), **kw)
+        six_m = pfield.fd_rf(1, 1, PITCH, FC, FS, C, [(0.0, 0.0)], pos, np.ones(1), T, n_sub=(2, 3), sub_mean=True,
+                             **kw)
+        # amplitude ratio from the energies (insensitive to the sub-sample arrival time)
+        ratios.append(math.sqrt(np.sum(six ** 2) / np.sum(one ** 2)))
+        ratios_mean.append(math.sqrt(np.sum(six_m ** 2) / np.sum(one ** 2)))
+    assert abs(ratios[0] - 36.0) < 1e-3 * 36.0
+    assert abs(ratios[1] - 36.0) < 0.25 * abs(ratios[0] - 36.0)
+    assert all(abs(r - 1.0) < 1e-4 for r in ratios_mean)
 
 
 def test_superposition_and_zero_amplitude():
