@@ -52,9 +52,12 @@ def knee_cutoff(lam: np.ndarray, floor: float = KNEE_FLOOR) -> int:
     d_k = 10 log10(max(lambda_k, floor lambda_1)/lambda_1), chord l_k from
     (1, d_1) to (N, d_N); k* = argmax over k in [2, N/2] of (l_k - d_k), the
     first index on ties; K = clamp(k* - 1, 1, N/2 - 1)  (k is 1-based).
-    The floor (-60 dB) keeps the rule on the part of the spectrum that a Gram
-    accumulated in FP32 or split-BF16 resolves (its eigenvalues are exact only
-    to ~1e-7 lambda_1); below it the spectrum is treated as flat."""
+    The floor (-60 dB): the cutoff is read off the singular-value curve by eye
+    (Section 3.2), and the power-Doppler results are shown over a 60 dB dynamic
+    range (Sections 3.1 and 3.3).  lambda_k is the energy of mode k, so modes more
+    than 60 dB below the leading one lie outside the range the method displays;
+    the rule reads the curve down to that level and treats the rest as flat (the
+    chord's far end is taken at no less than -60 dB)."""
     lam = np.asarray(lam, dtype=np.float64)
     N = lam.size
     if N < 4:
