@@ -110,8 +110,8 @@ int rf_synth(const fq_probe* probe, const fq_tx* tx, const fq_pulse* pulse, int3
  * fd_synth -- frequency-domain RF synthesis (Appendix D, Eq. 1 and Eq. 2; Algorithm 2):
  * every scatterer is a monopole; per frequency sample f_j = j df (df = fs / N,
  * N = n_samples + 2 ceil(6 s fs), s the pulse's Gaussian sigma) the element response is
- *   H_e(s, f) = (1/v) sum over the v = n_sub_x n_sub_y sub-elements (centres of a regular
- *               subdivision of the w_x x w_y element) of
+ *   H_e(s, f) = sum over the v = n_sub_x n_sub_y sub-elements (centres of a regular
+ *               subdivision of the w_x x w_y element; the coherent sum of Eq. 2) of
  *               (r_ref / r) e^{(i k - alpha) r} sinc(k b_x u_x) sinc(k b_y u_y),
  *   k = 2 pi f / c, b the sub-element half-widths, u the direction cosines towards the
  *   scatterer, sinc(x) = sin(x)/x (w = 0: no directivity), alpha from atten_db_cm_mhz;
@@ -209,8 +209,8 @@ int casorati_gram(const float* iq, int64_t n_vox, int32_t n_t, int32_t gram_mode
  * tridiagonalisation, implicit QL, back-transformation), rank selection, projection and
  * power Doppler (Section 2.4.2; Section 3.2 marks the cutoff on the singular-value curve).
  *  cutoff >= 0: K = cutoff; cutoff == FQ_CUTOFF_KNEE (-1): knee rule on the dB spectrum
- *     d_k = 10 log10(max(l_k, 1e-6 l_1)/l_1) (floored at -60 dB, the resolution of an
- *     FP32 / split-BF16 Gram), chord l from (1, d_1) to (N, d_N),
+ *     d_k = 10 log10(max(l_k, 1e-6 l_1)/l_1) (read down to -60 dB, the dynamic range over
+ *     which power Doppler is shown in Sections 3.1 and 3.3), chord l from (1, d_1) to (N, d_N),
  *     k* = argmax_{k in [2, N/2]} (chord_k - d_k) (first on ties), K = clamp(k*-1, 1, N/2-1);
  *  cutoff == FQ_CUTOFF_SSM (-2): K = the tissue rank that spatial_similarity (below) reads
  *     from the leading M = min(n_t, 64) spatial modes (K <= M/2).
@@ -353,6 +353,43 @@ int lcf_gather(const float* src, int64_t n_vox, int32_t n_t, int64_t n_vol, cons
 size_t fallback_workspace_size(int64_t n);
 int lcf_fallback(const float* pd_l, const float* pd_s, int64_t n, float tau_db, void* ws,
                  size_t ws_bytes, float* out, int32_t* flag, float* d_db, void* stream);
+
+/* ---------------------------------------------------------------------------------
+ * fq_workspace_size -- one query for every workspace the library takes.  Algorithm 3
+ * takes the available memory as an input and partitions the work to fit it; here every
+ * workspace is caller-owned, and this call gives its exact size for the given shapes.
+ *  which   FQ_WS_DAS       das_beamform / das_demodulate / das_delay_sum with every frame
+ *                          demodulated in one pass       (reads probe, tx, n_t, n_samples);
+ *          FQ_WS_DAS_MIN   das_beamform's smallest workspace (one block of 8 frames at a
+ *                          time; results identical)        (probe, tx, n_t, n_samples);
+ *          FQ_WS_GRAM      casorati_gram                   (n = voxels, n_t, gram_mode);
+ *          FQ_WS_SVD       svd_clutter_filter and hermitian_eig, every cutoff mode
+ *                                                          (n = voxels, n_t);
+ *          FQ_WS_SSM       spatial_similarity              (n = voxels, n_t);
+ *          FQ_WS_FD        fd_synth with blocks of n scatterers
+ *                                                          (probe, tx, pulse, fd, n, n_samples);
+ *          FQ_WS_DISPLAY   display_db                      (n = values);
+ *          FQ_WS_FALLBACK  lcf_fallback                    (n = values);
+ *          FQ_WS_LCF_ACT   the activation store of lcf_forward / lcf_backward
+ *                                                          (n = series, n_t);
+ *  params  HOST pointer to an fq_ws_query; fields a query does not read are ignored.
+ *  Returns the byte count (the same number as the per-call query named above), or 0 for
+ *  an unknown `which`, a NULL params or NULL struct pointer it needs, or sizes the entry
+ *  point would reject.  Pure host arithmetic: no device is touched.
+ * ------------------------------------------------------------------------------- */
+enum { FQ_WS_DAS = 0, FQ_WS_DAS_MIN = 1, FQ_WS_GRAM = 2, FQ_WS_SVD = 3, FQ_WS_SSM = 4, FQ_WS_FD = 5,
+       FQ_WS_DISPLAY = 6, FQ_WS_FALLBACK = 7, FQ_WS_LCF_ACT = 8 };
+typedef struct {
+    const fq_probe* probe;        /* FQ_WS_DAS, FQ_WS_DAS_MIN, FQ_WS_FD */
+    const fq_tx* tx;              /* FQ_WS_DAS, FQ_WS_DAS_MIN, FQ_WS_FD */
+    const fq_pulse* pulse;        /* FQ_WS_FD */
+    const fq_fd_params* fd;       /* FQ_WS_FD */
+    int64_t n;                    /* voxels, values, series or scatterers per block (see which) */
+    int32_t n_t;                  /* frames */
+    int32_t n_samples;            /* RF samples per trace */
+    int32_t gram_mode;            /* FQ_GRAM_* */
+} fq_ws_query;
+size_t fq_workspace_size(int32_t which, const void* params);
 
 /* Library identification and the thread-local message of the last failure. */
 int fq_version(void);

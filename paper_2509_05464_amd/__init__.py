@@ -16,4 +16,5 @@ from ._lib import (  # noqa: F401
     display_workspace_size, display_db, mip, image_quality,
     lcf_act_size, lcf_forward, lcf_backward, lcf_adam_step, lcf_gather,
     fallback_workspace_size, lcf_fallback,
+    fq_workspace_size, WS_DAS, WS_DAS_MIN, WS_GRAM, WS_SVD, WS_SSM, WS_FD, WS_DISPLAY, WS_FALLBACK, WS_LCF_ACT,
 )

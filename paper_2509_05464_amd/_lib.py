@@ -65,6 +65,15 @@ def make_fd_params(elem_width=(0.0, 0.0), n_sub=(1, 1), atten_db_cm_mhz=0.0, spe
     return FdParams(elem_width[0], elem_width[1], n_sub[0], n_sub[1], atten_db_cm_mhz, spectral_floor)
 
 
+WS_DAS, WS_DAS_MIN, WS_GRAM, WS_SVD, WS_SSM, WS_FD, WS_DISPLAY, WS_FALLBACK, WS_LCF_ACT = range(9)
+
+
+class WsQuery(ctypes.Structure):
+    _fields_ = [('probe', ctypes.POINTER(Probe)), ('tx', ctypes.POINTER(Tx)), ('pulse', ctypes.POINTER(Pulse)),
+                ('fd', ctypes.POINTER(FdParams)), ('n', ctypes.c_int64), ('n_t', ctypes.c_int32),
+                ('n_samples', ctypes.c_int32), ('gram_mode', ctypes.c_int32)]
+
+
 def make_probe(nx_el, ny_el, pitch_x, pitch_y, fc, fs, c) -> Probe:
     return Probe(nx_el, ny_el, pitch_x, pitch_y, fc, fs, c)
 
@@ -121,6 +130,7 @@ _SIGS = {
     'lcf_gather': (ctypes.c_int, [_vp, _i64, _i32, _i64, _vp, _i64, _vp, _vp]),
     'fallback_workspace_size': (_sz, [_i64]),
     'lcf_fallback': (ctypes.c_int, [_vp, _vp, _i64, _f32, _vp, _sz, _vp, _vp, _vp, _vp]),
+    'fq_workspace_size': (_sz, [_i32, _vp]),
     'fq_version': (ctypes.c_int, []),
     'fq_last_error': (ctypes.c_char_p, []),
 }
@@ -219,6 +229,19 @@ def das_delay_sum(probe: Probe, tx: Tx, grid: Grid, n_samples: int, ws: torch.Te
     st = lib().das_delay_sum(ctypes.byref(probe), ctypes.byref(tx), ctypes.byref(grid), F, n_samples, interp,
                              _ptr(ws), ws.numel() * ws.element_size(), _ptr(_f32view(iq)), _stream())
     _check('das_delay_sum', st)
+
+
+def fq_workspace_size(which: int, probe: Optional[Probe] = None, tx: Optional[Tx] = None,
+                      pulse: Optional[Pulse] = None, fdp: Optional[FdParams] = None, n: int = 0, n_t: int = 0,
+                      n_samples: int = 0, gram_mode: int = GRAM_FP32) -> int:
+    """The one workspace query of the library (WS_* selects the entry point)."""
+    q = WsQuery()
+    q.probe = ctypes.pointer(probe) if probe is not None else None
+    q.tx = ctypes.pointer(tx) if tx is not None else None
+    q.pulse = ctypes.pointer(pulse) if pulse is not None else None
+    q.fd = ctypes.pointer(fdp) if fdp is not None else None
+    q.n, q.n_t, q.n_samples, q.gram_mode = n, n_t, n_samples, gram_mode
+    return lib().fq_workspace_size(which, ctypes.byref(q))
 
 
 def gram_workspace_size(n_vox: int, n_t: int, mode: int = GRAM_FP32) -> int:

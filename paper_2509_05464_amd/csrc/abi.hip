@@ -36,3 +36,32 @@ int zero_async(void* p, size_t n_bytes, hipStream_t s) {
 extern "C" int fq_version(void) { return 1; }
 
 extern "C" const char* fq_last_error(void) { return fq::g_err; }
+
+// One dispatching query over the per-call workspace sizes (pure host arithmetic).
+extern "C" size_t fq_workspace_size(int32_t which, const void* params) {
+    if (!params) return 0;
+    const fq_ws_query& q = *static_cast<const fq_ws_query*>(params);
+    switch (which) {
+        case FQ_WS_DAS:
+        case FQ_WS_DAS_MIN:
+            if (!q.probe || !q.tx) return 0;
+            return das_workspace_size(q.probe, q.tx, q.n_t, q.n_samples, which == FQ_WS_DAS_MIN ? 1 : 0);
+        case FQ_WS_GRAM:
+            return gram_workspace_size(q.n, q.n_t, q.gram_mode);
+        case FQ_WS_SVD:
+            return svd_workspace_size(q.n, q.n_t);
+        case FQ_WS_SSM:
+            return ssm_workspace_size(q.n, q.n_t);
+        case FQ_WS_FD:
+            if (!q.probe || !q.tx || !q.pulse || !q.fd) return 0;
+            return fd_workspace_size(q.probe, q.tx, q.pulse, q.fd, q.n_samples, q.n);
+        case FQ_WS_DISPLAY:
+            return display_workspace_size(q.n);
+        case FQ_WS_FALLBACK:
+            return fallback_workspace_size(q.n);
+        case FQ_WS_LCF_ACT:
+            return lcf_act_size(q.n, q.n_t);
+        default:
+            return 0;
+    }
+}

@@ -29,7 +29,7 @@ def lib():
 def test_header_declares_the_path():
     names = declared()
     for want in ('rf_synth', 'das_beamform', 'casorati_gram', 'svd_clutter_filter', 'power_doppler',
-                 'lcf_forward', 'lcf_backward', 'lcf_adam_step', 'fq_last_error'):
+                 'lcf_forward', 'lcf_backward', 'lcf_adam_step', 'fq_workspace_size', 'fq_last_error'):
         assert want in names
 
 
@@ -68,6 +68,41 @@ def test_workspace_queries_without_gpu(lib):
     assert fq.ssm_workspace_size(100, 20) < ssm
     assert fq.svd_workspace_size(acq.n_vox, acq.n_frames) > ssm
     assert fq.lcf_act_size(4096, 200) > 4096 * 200 * 194 * 2
+
+
+def test_one_workspace_query_matches_the_per_call_queries(lib):
+    """fq_workspace_size dispatches to the per-call queries; unknown kinds, a NULL query or
+    a missing struct give 0 (host arithmetic only)."""
+    import ctypes
+    import paper_2509_05464_amd as fq
+    from fqscene import get_config
+    for name in ('c1', 'c2', 'c5'):
+        acq = get_config(name).acq
+        probe = fq.make_probe(acq.nx_el, acq.ny_el, acq.pitch, acq.pitch, acq.fc, acq.fs, acq.c)
+        tx = fq.make_tx(acq.tilts_rad())
+        F, T, NV = acq.n_frames, acq.n_samples, acq.n_vox
+        assert fq.fq_workspace_size(fq.WS_DAS, probe, tx, n_t=F, n_samples=T) == \
+            fq.das_workspace_size(probe, tx, F, T, False) > 0
+        assert fq.fq_workspace_size(fq.WS_DAS_MIN, probe, tx, n_t=F, n_samples=T) == \
+            fq.das_workspace_size(probe, tx, F, T, True) > 0
+        for mode in (fq.GRAM_FP32, fq.GRAM_SPLIT_BF16, fq.GRAM_SPLIT4_BF16, fq.GRAM_BF16):
+            assert fq.fq_workspace_size(fq.WS_GRAM, n=NV, n_t=F, gram_mode=mode) == \
+                fq.gram_workspace_size(NV, F, mode) > 0
+        assert fq.fq_workspace_size(fq.WS_SVD, n=NV, n_t=F) == fq.svd_workspace_size(NV, F) > 0
+        assert fq.fq_workspace_size(fq.WS_SSM, n=NV, n_t=F) == fq.ssm_workspace_size(NV, F) > 0
+        assert fq.fq_workspace_size(fq.WS_DISPLAY, n=NV) == fq.display_workspace_size(NV) > 0
+        assert fq.fq_workspace_size(fq.WS_FALLBACK, n=NV) == fq.fallback_workspace_size(NV) > 0
+        assert fq.fq_workspace_size(fq.WS_LCF_ACT, n=4096, n_t=F) == fq.lcf_act_size(4096, F) > 0
+        pulse = fq.make_pulse()
+        fdp = fq.make_fd_params((0.27e-3, 0.27e-3), (2, 2), 0.5)
+        assert fq.fq_workspace_size(fq.WS_FD, probe, tx, pulse, fdp, n=1000, n_samples=T) == \
+            fq.fd_workspace_size(probe, tx, pulse, fdp, T, 1000) > 0
+        # a query without the structs it reads
+        assert fq.fq_workspace_size(fq.WS_DAS, n_t=F, n_samples=T) == 0
+        assert fq.fq_workspace_size(fq.WS_FD, probe, tx, n=1000, n_samples=T) == 0
+    assert fq.fq_workspace_size(99, n=10, n_t=4) == 0
+    assert fq.fq_workspace_size(fq.WS_GRAM, n=0, n_t=4) == 0
+    assert lib.fq_workspace_size(fq.WS_GRAM, None) == 0
 
 
 def test_invalid_arguments_return_status(lib):
