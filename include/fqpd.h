@@ -50,6 +50,7 @@ enum { FQ_GRAM_FP32 = 0, FQ_GRAM_SPLIT_BF16 = 1, FQ_GRAM_BF16 = 2, FQ_GRAM_SPLIT
 enum { FQ_CUTOFF_KNEE = -1, FQ_CUTOFF_SSM = -2 };
 enum { FQ_DISP_POWER = 0, FQ_DISP_IQ = 1, FQ_DISP_UNIT = 2 };
 enum { FQ_MIP_XY = 0, FQ_MIP_XZ = 1, FQ_MIP_YZ = 2 };
+enum { FQ_PROBE_LDS_READ = 0, FQ_PROBE_FP32_FMA = 1 };
 
 typedef struct {
     int32_t nx_el, ny_el;     /* regular matrix array, nx_el*ny_el elements */
@@ -183,6 +184,15 @@ int das_delay_sum(const fq_probe* probe, const fq_tx* tx, const fq_grid* grid, i
                   int32_t n_samples, int32_t interp, const void* ws, size_t ws_bytes, float* iq,
                   void* stream);
 
+/* Host-only query (no device work): the delay rows per (transmit, element) that
+ * das_delay_sum stages on chip for one 16 x 16 x 4-voxel tile.  The bound is the
+ * tile's diameter (receive distances are 1-Lipschitz in the voxel position) plus the
+ * transmit-plane spread over the tile, in samples, plus 8 rows of margin for the
+ * interpolation taps and the integer/fraction splits, rounded up to a multiple of 8.
+ * Every tap of every voxel of a tile falls inside its window.  Returns -1 (and sets
+ * the error text) for invalid arguments. */
+int das_window_rows(const fq_probe* probe, const fq_tx* tx, const fq_grid* grid);
+
 /* ---------------------------------------------------------------------------------
  * casorati_gram -- G = S^H S for the Casorati matrix S[v][f] = iq[f][v] (Section 2.4.2:
  * the SVD clutter filter works on S; its right singular vectors and squared singular
@@ -206,8 +216,10 @@ int casorati_gram(const float* iq, int64_t n_vox, int32_t n_t, int32_t gram_mode
 
 /* ---------------------------------------------------------------------------------
  * svd_clutter_filter -- eigendecomposition of G in FP64 on the GPU (Householder
- * tridiagonalisation, implicit QL, back-transformation), rank selection, projection and
- * power Doppler (Section 2.4.2; Section 3.2 marks the cutoff on the singular-value curve).
+ * tridiagonalisation; every eigenvalue by multisection on Sturm counts; the K wanted
+ * eigenvectors by inverse iteration, orthogonalised inside clusters of close eigenvalues;
+ * back-transformation), rank selection, projection and power Doppler on the matrix cores
+ * (Section 2.4.2; Section 3.2 marks the cutoff on the singular-value curve).
  *  cutoff >= 0: K = cutoff; cutoff == FQ_CUTOFF_KNEE (-1): knee rule on the dB spectrum
  *     d_k = 10 log10(max(l_k, 1e-6 l_1)/l_1) (read down to -60 dB, the dynamic range over
  *     which power Doppler is shown in Sections 3.1 and 3.3), chord l from (1, d_1) to (N, d_N),
@@ -219,8 +231,8 @@ int casorati_gram(const float* iq, int64_t n_vox, int32_t n_t, int32_t gram_mode
  *  iq_filt  complex64 [n_t][n_vox] or NULL;  pd float32 [n_vox] or NULL;
  *  sigma    float64 [n_t] singular values, descending (device);
  *  k_used   int32 [1] (device): the K applied;
- *  status   int32 [1] (device) or NULL: 0 ok, FQ_E_NUMERIC if the QL iteration did not
- *           converge within 60 iterations per eigenvalue (outputs are then undefined).
+ *  status   int32 [1] (device) or NULL: 0 ok, FQ_E_NUMERIC if an inverse-iteration vector
+ *           vanished or overflowed (outputs are then undefined).
  *  K is limited to 64 (FQ_E_INVALID for a larger fixed cutoff; the knee result is
  *  clamped to 64 and the status word set to FQ_E_NUMERIC).
  * ------------------------------------------------------------------------------- */
@@ -230,9 +242,11 @@ int svd_clutter_filter(const float* iq, int64_t n_vox, int32_t n_t, const double
                        int32_t cutoff, void* ws, size_t ws_bytes, float* iq_filt, float* pd,
                        double* sigma, int32_t* k_used, int32_t* status, void* stream);
 
-/* eigendecomposition only: lam float64 [n_t] descending (clamped >= 0), vecs complex128
- * [n_t][n_t] with column k the eigenvector of lam[k], or NULL for eigenvalues only.
- * Same workspace and status word as above. */
+/* eigendecomposition only, every eigenvector (implicit QL with Wilkinson shifts on the
+ * tridiagonal matrix, the rotations replayed on the identity): lam float64 [n_t]
+ * descending (clamped >= 0), vecs complex128 [n_t][n_t] with column k the eigenvector of
+ * lam[k], or NULL for eigenvalues only.  Same workspace as above; the status word is
+ * FQ_E_NUMERIC if the QL iteration did not converge within 60 iterations per eigenvalue. */
 int hermitian_eig(const double* gram, int32_t n_t, void* ws, size_t ws_bytes, double* lam,
                   double* vecs, int32_t* status, void* stream);
 
@@ -391,8 +405,20 @@ typedef struct {
 } fq_ws_query;
 size_t fq_workspace_size(int32_t which, const void* params);
 
+/* ---------------------------------------------------------------------------------
+ * roof_probe -- measurement helper, not a step of the path: the on-chip ceilings the
+ * kernels are priced against.  FQ_PROBE_LDS_READ: every thread of n_blocks workgroups of
+ * 256 reads 8 x iters 16-byte LDS slots (conflict-free; 64 KB buffer per workgroup), so
+ * the launch moves n_blocks * 256 * 128 * iters bytes from LDS to registers;
+ * FQ_PROBE_FP32_FMA: every thread runs 8 independent FMA chains of 16 * iters steps
+ * (n_blocks * 256 * 256 * iters FLOP).  The caller times the launch on `stream`.
+ *  out   float32 [n_blocks * 256] (folded results, so nothing is optimised away).
+ *  Errors: FQ_E_INVALID for a bad selector, sizes or pointer. */
+int roof_probe(int32_t which, int32_t n_blocks, int32_t iters, float* out, void* stream);
+
 /* Library identification and the thread-local message of the last failure. */
 int fq_version(void);
+
 const char* fq_last_error(void);
 
 #ifdef __cplusplus

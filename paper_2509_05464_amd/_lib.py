@@ -111,6 +111,7 @@ _SIGS = {
     'das_beamform': (ctypes.c_int, [_P(Probe), _P(Tx), _P(Grid), _i32, _i32, _vp, _i32, _vp, _sz, _vp, _vp]),
     'das_demodulate': (ctypes.c_int, [_P(Probe), _P(Tx), _i32, _i32, _vp, _vp, _sz, _vp]),
     'das_delay_sum': (ctypes.c_int, [_P(Probe), _P(Tx), _P(Grid), _i32, _i32, _i32, _vp, _sz, _vp, _vp]),
+    'das_window_rows': (ctypes.c_int, [_P(Probe), _P(Tx), _P(Grid)]),
     'gram_workspace_size': (_sz, [_i64, _i32, _i32]),
     'casorati_gram': (ctypes.c_int, [_vp, _i64, _i32, _i32, _vp, _sz, _vp, _vp]),
     'svd_workspace_size': (_sz, [_i64, _i32]),
@@ -131,6 +132,7 @@ _SIGS = {
     'fallback_workspace_size': (_sz, [_i64]),
     'lcf_fallback': (ctypes.c_int, [_vp, _vp, _i64, _f32, _vp, _sz, _vp, _vp, _vp, _vp]),
     'fq_workspace_size': (_sz, [_i32, _vp]),
+    'roof_probe': (ctypes.c_int, [_i32, _i32, _i32, _vp, _vp]),
     'fq_version': (ctypes.c_int, []),
     'fq_last_error': (ctypes.c_char_p, []),
 }
@@ -207,6 +209,14 @@ def das_workspace_size(probe: Probe, tx: Tx, n_frames: int, n_samples: int, mini
     return lib().das_workspace_size(ctypes.byref(probe), ctypes.byref(tx), n_frames, n_samples, int(minimum))
 
 
+def das_window_rows(probe: Probe, tx: Tx, grid: Grid) -> int:
+    """Delay rows staged on chip per (transmit, element) for one voxel tile (host query)."""
+    w = lib().das_window_rows(ctypes.byref(probe), ctypes.byref(tx), ctypes.byref(grid))
+    if w < 0:
+        _check("das_window_rows", FQ_E_INVALID)
+    return int(w)
+
+
 def das_beamform(probe: Probe, tx: Tx, grid: Grid, rf: torch.Tensor, iq: torch.Tensor, ws: torch.Tensor,
                  interp: int = INTERP_LINEAR) -> None:
     """rf float32 [F][A][E][T] -> iq complex64 [F][Nv]."""
@@ -254,6 +264,16 @@ def casorati_gram(iq: torch.Tensor, gram: torch.Tensor, ws: torch.Tensor, mode: 
     st = lib().casorati_gram(_ptr(_f32view(iq)), nv, nt, mode, _ptr(ws), ws.numel() * ws.element_size(),
                              _ptr(_f32view(gram)), _stream())
     _check('casorati_gram', st)
+
+
+PROBE_LDS_READ, PROBE_FP32_FMA = 0, 1
+
+
+def roof_probe(which: int, out: torch.Tensor, iters: int) -> None:
+    """Launch an on-chip ceiling probe over out.numel() / 256 workgroups (measurement helper)."""
+    n_blocks = out.numel() // 256
+    st = lib().roof_probe(which, n_blocks, iters, _ptr(out), _stream())
+    _check('roof_probe', st)
 
 
 def svd_workspace_size(n_vox: int, n_t: int) -> int:

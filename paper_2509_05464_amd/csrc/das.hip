@@ -78,6 +78,9 @@ struct DasArgs {
     float2* iq;            // [F][Nv]
     int nx, ny, nz;
     int ntx, nty;          // tiles along x, y
+    int64_t ntiles;        // tiles of the grid
+    int64_t nwork;         // (tile, frame block) pairs of this launch
+    int64_t per_xcd;       // pairs given to each XCD: ceil(nwork / 8)
     double x0, y0, z0, dx, dy, dz;
     int nx_el;
     double pitch_x, pitch_y;
@@ -100,9 +103,15 @@ __global__ void __launch_bounds__(DAS_THREADS) das_kernel(const DasArgs a) {
     extern __shared__ float4 win[];            // [AT][W][ROW_F4]
     __shared__ int nlo_s[MAX_AT];
 
-    const int tile = blockIdx.x;
+    // Workgroup id -> (tile, frame block): the hardware deals workgroups to the 8 XCDs in
+    // turn (id mod 8), so XCD x receives a contiguous run of the (frame block, tile) order,
+    // tiles fastest; the tiles that run together on one XCD are neighbours in space and read
+    // overlapping delay windows of the same traces through that XCD's L2.
+    const int64_t g = (int64_t)(blockIdx.x % 8) * a.per_xcd + blockIdx.x / 8;
+    if (g >= a.nwork) return;
+    const int tile = (int)(g % a.ntiles);
     const int txi = tile % a.ntx, tyi = (tile / a.ntx) % a.nty, tzi = tile / (a.ntx * a.nty);
-    const int fbl = blockIdx.y;
+    const int fbl = (int)(g / a.ntiles);
     const int fb = a.fb0 + fbl;
     const int lx = threadIdx.x % TILE_X, ly = threadIdx.x / TILE_X;
     const int ix = txi * TILE_X + lx, iy = tyi * TILE_Y + ly, iz0 = tzi * VZ;
@@ -191,6 +200,13 @@ __global__ void __launch_bounds__(DAS_THREADS) das_kernel(const DasArgs a) {
                 const float sf = floorf(s);
                 const float al = s - sf;
                 int row = ntx[j] + nrx[k] + (int)sf - base + J0;
+#ifdef FQ_DEBUG_WINDOW
+                // debug builds: a tap outside the staged window poisons the voxel
+                if (row < 0 || row > a.W - NT) acc[k][0].x = __builtin_nanf("");
+#endif
+                // The window bound (window_rows) covers every tap of the tile, so the clamp
+                // never engages (checked on the host for the workload geometries and extreme
+                // tilts); it keeps the LDS reads in bounds whatever the input.
                 row = min(max(row, 0), a.W - NT);
                 float2 P = cmul(ptx[j], prx[k]);
                 if (k > 0) P = cmul(P, a.zeta[j][k]);
@@ -325,6 +341,16 @@ extern "C" size_t das_workspace_size(const fq_probe* probe, const fq_tx* tx, int
     return minimum ? b : b * nfb;
 }
 
+extern "C" int das_window_rows(const fq_probe* probe, const fq_tx* tx, const fq_grid* grid) {
+    if (check_probe_tx(probe, tx) != FQ_OK) return -1;
+    if (!grid || grid->nx < 1 || grid->ny < 1 || grid->nz < 1 || !(grid->dx > 0) || !(grid->dy > 0) ||
+        !(grid->dz > 0)) {
+        set_error("bad grid");
+        return -1;
+    }
+    return window_rows(*grid, make_tx(*probe, *tx), probe->fs_hz / probe->c_mps);
+}
+
 namespace fq {
 namespace {
 
@@ -407,6 +433,7 @@ int das_prepare(const fq_probe* probe, const fq_tx* tx, const fq_grid* grid, int
     da.inv_A = 1.0f / (float)P.A;
     P.ntiles = (int64_t)da.ntx * da.nty * ntz;
     FQ_REQUIRE(P.ntiles < (1LL << 31), "grid too large");
+    da.ntiles = P.ntiles;
     return FQ_OK;
 }
 
@@ -420,6 +447,9 @@ int launch_demod(DasPlan& P, int fb0, int nb, hipStream_t s) {
 int launch_das(DasPlan& P, int fb0, int nb, int interp, const fq_grid* grid, double fs_hz, hipStream_t s) {
     DasArgs& da = P.da;
     da.fb0 = fb0;
+    da.nwork = P.ntiles * nb;
+    da.per_xcd = (da.nwork + 7) / 8;
+    FQ_REQUIRE(8 * da.per_xcd * DAS_THREADS < (1LL << 32), "grid too large");
     for (int a0 = 0; a0 < P.A; a0 += P.at) {
         const int na = std::min(P.at, P.A - a0);
         da.a0 = a0;
@@ -440,7 +470,7 @@ int launch_das(DasPlan& P, int fb0, int nb, int interp, const fq_grid* grid, dou
             }
         }
         const size_t lds = P.row_bytes * (size_t)P.W * na;
-        hipLaunchKernelGGL(das_fn(na, interp), dim3((unsigned)P.ntiles, nb), dim3(DAS_THREADS), lds, s, da);
+        hipLaunchKernelGGL(das_fn(na, interp), dim3((unsigned)(8 * da.per_xcd)), dim3(DAS_THREADS), lds, s, da);
         FQ_LAUNCH_CHECK();
     }
     return FQ_OK;

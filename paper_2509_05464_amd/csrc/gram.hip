@@ -1,13 +1,16 @@
 // casorati_gram: G = S^H S of the Casorati matrix on the gfx950 matrix cores.
 //
 // With S = A + iB (voxels x frames), Re G = A^T A + B^T B and Im G = A^T B - B^T A.
-// G is Hermitian, so only the 32x32 frame tiles (I, J) with I <= J are formed.  One
-// workgroup owns one tile and one voxel range (split over the contraction dimension);
-// its four waves form the four real products Re.Re, Im.Im, Re.Im and Im.Re of the tile
-// with MFMA, reading 64-voxel slices of the 64 frames involved from LDS.
+// G is Hermitian, so only the 32x32 frame tiles (I, J) with I <= J are formed.  A
+// workgroup owns a 2x2 group of tiles (64 frames of I-blocks by 64 frames of J-blocks)
+// and one voxel range (split over the contraction dimension): each 64-voxel stage of the
+// 128 frames involved (64 on the group's diagonal) is staged in LDS once, and each of
+// the four waves forms the four real products Re.Re, Im.Im, Re.Im and Im.Re of its own
+// tile with MFMA, so every staged value feeds two tiles' products.
 //   FP32 mode       : v_mfma_f32_32x32x2_f32.
 //   split-BF16 mode : x = hi + lo with hi = bf16(x), lo = bf16(x - hi) (round to nearest
-//                     even); three v_mfma_f32_32x32x16_bf16 products hi.hi + hi.lo + lo.hi.
+//                     even), split once when the stage is written to LDS; three
+//                     v_mfma_f32_32x32x16_bf16 products hi.hi + hi.lo + lo.hi.
 //   split-BF16 x4   : hi.hi + hi.lo + lo.hi + lo.lo.  The three-product form drops
 //                     sum_v lo lo^H, a positive semi-definite term of about 2^-18 of the
 //                     Gram's trace that biases every eigenvalue below that level; the
@@ -19,7 +22,7 @@
 // needs); the partial tiles of all voxel ranges are then summed in FP64 in a fixed
 // order (deterministic).
 // Workgroups that share a voxel range are placed on the same XCD so the range is read
-// from HBM once and served to the other tiles from that XCD's L2.
+// from HBM once and served to the other groups from that XCD's L2.
 #include "fq_common.hpp"
 
 namespace fq {
@@ -27,21 +30,23 @@ namespace {
 
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef unsigned short ushortx8 __attribute__((ext_vector_type(8)));
 
 constexpr int GT = 32;            // tile edge, frames
+constexpr int GG = 2;             // tiles per group edge
+constexpr int GR = GG * GT;       // frames per group edge
 constexpr int KC = 64;            // voxels per LDS stage
-constexpr int LDW = KC + 4;       // LDS row stride (floats)
-constexpr int FLUSH = 1;          // stages per FP32 accumulation block (64 voxels)
+constexpr int LDW = KC + 4;       // FP32 LDS row stride (floats)
+constexpr int LDB = KC + 8;       // BF16 LDS row stride (bf16 values; 144-byte rows)
 constexpr int GRAM_THREADS = 256;
 constexpr int NXCD = 8;
 
 struct GramArgs {
     const float2* iq;     // [nt][nv]
-    double* part;         // [nsplit][ntiles][4][GT*GT]
+    double* part;         // [nsplit][ntiles][2][GT*GT]: Re G, Im G partial tiles
     int64_t nv;
     int64_t chunk;        // voxels per split
     int nt, nb, ntiles, nsplit;
+    int nbg, ngroups;     // tile groups per edge, groups in the upper triangle
 };
 
 __device__ __forceinline__ void tile_ij(int t, int nb, int& I, int& J) {
@@ -62,124 +67,184 @@ __device__ __forceinline__ unsigned short bf16_rne_bits(float x) {
 
 __device__ __forceinline__ float bf16_to_f32(unsigned short b) { return __uint_as_float((unsigned int)b << 16); }
 
+// hi/lo pair of 8 values packed as two 16-byte vectors of bf16 bit patterns
+__device__ __forceinline__ void split8(const float* x, uint4& hi, uint4& lo) {
+    unsigned int h[4], l[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const unsigned short h0 = bf16_rne_bits(x[2 * q]), h1 = bf16_rne_bits(x[2 * q + 1]);
+        const unsigned short l0 = bf16_rne_bits(x[2 * q] - bf16_to_f32(h0));
+        const unsigned short l1 = bf16_rne_bits(x[2 * q + 1] - bf16_to_f32(h1));
+        h[q] = (unsigned int)h0 | ((unsigned int)h1 << 16);
+        l[q] = (unsigned int)l0 | ((unsigned int)l1 << 16);
+    }
+    hi = make_uint4(h[0], h[1], h[2], h[3]);
+    lo = make_uint4(l[0], l[1], l[2], l[3]);
+}
+
+// flip the sign bits of 8 packed bf16 values
+__device__ __forceinline__ uint4 neg8(uint4 x) {
+    return make_uint4(x.x ^ 0x80008000u, x.y ^ 0x80008000u, x.z ^ 0x80008000u, x.w ^ 0x80008000u);
+}
+
 template <int MODE>
-__global__ void __launch_bounds__(GRAM_THREADS) gram_kernel(const GramArgs a) {
-    __shared__ float sRe[2 * GT * LDW];
-    __shared__ float sIm[2 * GT * LDW];
+__global__ void __launch_bounds__(GRAM_THREADS, 2) gram_kernel(const GramArgs a) {
+    constexpr bool SPLIT = MODE != FQ_GRAM_FP32;
+    // FP32: planes Re, Im of [2 GR][LDW] floats; BF16: planes Re.hi, Re.lo, Im.hi, Im.lo of [2 GR][LDB]
+    constexpr int PLANE = SPLIT ? 2 * GR * LDB * 2 : 2 * GR * LDW * 4;   // bytes
+    constexpr int NPLANE = SPLIT ? 4 : 2;
+    __shared__ __align__(16) unsigned char lds[NPLANE * PLANE];
 
     // XCD-aware decode: workgroups id, id+8, ... run on one XCD; give them one voxel range.
     const int id = blockIdx.x;
     const int xcd = id % NXCD, loc = id / NXCD;
-    const int t = loc % a.ntiles;
-    const int split = (loc / a.ntiles) * NXCD + xcd;
+    const int grp = loc % a.ngroups;
+    const int split = (loc / a.ngroups) * NXCD + xcd;
     if (split >= a.nsplit) return;
-    int I, J;
-    tile_ij(t, a.nb, I, J);
+    int gi, gj;
+    tile_ij(grp, a.nbg, gi, gj);
+    const bool diag = gi == gj;
     const int64_t v_begin = (int64_t)split * a.chunk;
     const int64_t v_end = min(a.nv, v_begin + a.chunk);
 
     const int w = threadIdx.x / 64, l = threadIdx.x % 64;
-    const float* X = (w == 0 || w == 2) ? sRe : sIm;          // rows of block I
-    const float* Y = ((w == 0 || w == 3) ? sRe : sIm) + GT * LDW;   // rows of block J
+    const int pi = w / GG, qj = w % GG;
+    const int I = gi * GG + pi, J = gj * GG + qj;
+    const bool active = I <= J && J < a.nb;      // the group's lower tile on the diagonal is skipped
+    const int xrow = pi * GT;                    // stage rows of block I
+    const int yrow = (diag ? 0 : GR) + qj * GT;  // stage rows of block J (shared with I on the diagonal)
 
-    floatx16 acc;
-    double acc64[16];
+    // Re G = Re.Re + Im.Im and Im G = Re.Im - Im.Re accumulate directly (the second term of
+    // Im G through a negated operand): FP32 within a stage, FP64 across stages
+    floatx16 acc_re, acc_im;
+    double sum_re[16], sum_im[16];
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
-        acc[r] = 0.0f;
-        acc64[r] = 0.0;
+        acc_re[r] = acc_im[r] = 0.0f;
+        sum_re[r] = sum_im[r] = 0.0;
     }
 
-    // loader mapping: 64 rows x 64 voxels; thread -> (row, 16-voxel quarter)
-    const int lrow = threadIdx.x / 4, lq = threadIdx.x % 4;
-    const int frame = lrow < GT ? I * GT + lrow : J * GT + (lrow - GT);
-    const float4* src = reinterpret_cast<const float4*>(a.iq + (int64_t)frame * a.nv);
-
-    int stage = 0;
-    for (int64_t v0 = v_begin; v0 < v_end; v0 += KC, ++stage) {
-        __syncthreads();
-        {
-            float re[16], im[16];
-            const int64_t vb = v0 + lq * 16;
-            if (frame < a.nt && vb + 16 <= v_end && (a.nv % 2) == 0) {
+    // loader mapping: up to 128 rows x 64 voxels; thread -> (row, 32-voxel half).  The next
+    // stage is loaded into registers while the current one is multiplied.
+    const int lrow = threadIdx.x >> 1, lh = threadIdx.x & 1;
+    const bool lact = lrow < (diag ? GR : 2 * GR);
+    const int frame = lrow < GR ? gi * GR + lrow : gj * GR + (lrow - GR);
+    const bool fvalid = lact && frame < a.nt;
+    const float2* srow = a.iq + (int64_t)(fvalid ? frame : 0) * a.nv;
+    float re[32], im[32];
+    auto load = [&](int64_t v0) {
+        const int64_t vb = v0 + lh * 32;
+        if (fvalid && vb + 32 <= v_end && (a.nv % 2) == 0) {
+            const float4* src = reinterpret_cast<const float4*>(srow + vb);
 #pragma unroll
-                for (int q = 0; q < 8; ++q) {
-                    const float4 p = src[(vb >> 1) + q];
-                    re[2 * q] = p.x;
-                    im[2 * q] = p.y;
-                    re[2 * q + 1] = p.z;
-                    im[2 * q + 1] = p.w;
-                }
-            } else {
-#pragma unroll
-                for (int q = 0; q < 16; ++q) {
-                    float2 p = make_float2(0.f, 0.f);
-                    if (frame < a.nt && vb + q < v_end) p = a.iq[(int64_t)frame * a.nv + vb + q];
-                    re[q] = p.x;
-                    im[q] = p.y;
-                }
-            }
-            float* dr = sRe + lrow * LDW + lq * 16;
-            float* di = sIm + lrow * LDW + lq * 16;
-#pragma unroll
-            for (int q = 0; q < 16; q += 4) {
-                *reinterpret_cast<float4*>(dr + q) = make_float4(re[q], re[q + 1], re[q + 2], re[q + 3]);
-                *reinterpret_cast<float4*>(di + q) = make_float4(im[q], im[q + 1], im[q + 2], im[q + 3]);
-            }
-        }
-        __syncthreads();
-        const int i = l % 32, h = l / 32;
-        if (MODE == FQ_GRAM_FP32) {
-#pragma unroll
-            for (int kk = 0; kk < KC; kk += 2) {
-                const float av = X[i * LDW + kk + h];
-                const float bv = Y[i * LDW + kk + h];
-                acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, acc, 0, 0, 0);
+            for (int q = 0; q < 16; ++q) {
+                const float4 p = src[q];
+                re[2 * q] = p.x;
+                im[2 * q] = p.y;
+                re[2 * q + 1] = p.z;
+                im[2 * q + 1] = p.w;
             }
         } else {
 #pragma unroll
-            for (int kk = 0; kk < KC; kk += 16) {
-                const float4* xp = reinterpret_cast<const float4*>(X + i * LDW + kk + h * 8);
-                const float4* yp = reinterpret_cast<const float4*>(Y + i * LDW + kk + h * 8);
-                const float4 x0 = xp[0], x1 = xp[1], y0 = yp[0], y1 = yp[1];
-                const float xs[8] = {x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
-                const float ys[8] = {y0.x, y0.y, y0.z, y0.w, y1.x, y1.y, y1.z, y1.w};
-                ushortx8 xh, xl, yh, yl;
+            for (int q = 0; q < 32; ++q) {
+                float2 p = make_float2(0.f, 0.f);
+                if (fvalid && vb + q < v_end) p = srow[vb + q];
+                re[q] = p.x;
+                im[q] = p.y;
+            }
+        }
+    };
+    if (lact && v_begin < v_end) load(v_begin);
+
+    const int i = l % 32, h = l / 32;
+    for (int64_t v0 = v_begin; v0 < v_end; v0 += KC) {
+        __syncthreads();
+        if (lact) {
+            if (!SPLIT) {
+                float* dr = reinterpret_cast<float*>(lds) + lrow * LDW + lh * 32;
+                float* di = reinterpret_cast<float*>(lds + PLANE) + lrow * LDW + lh * 32;
 #pragma unroll
-                for (int q = 0; q < 8; ++q) {
-                    xh[q] = bf16_rne_bits(xs[q]);
-                    yh[q] = bf16_rne_bits(ys[q]);
-                    xl[q] = bf16_rne_bits(xs[q] - bf16_to_f32(xh[q]));
-                    yl[q] = bf16_rne_bits(ys[q] - bf16_to_f32(yh[q]));
+                for (int q = 0; q < 32; q += 4) {
+                    *reinterpret_cast<float4*>(dr + q) = make_float4(re[q], re[q + 1], re[q + 2], re[q + 3]);
+                    *reinterpret_cast<float4*>(di + q) = make_float4(im[q], im[q + 1], im[q + 2], im[q + 3]);
                 }
-                const bf16x8 XH = __builtin_bit_cast(bf16x8, xh), YH = __builtin_bit_cast(bf16x8, yh);
-                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(XH, YH, acc, 0, 0, 0);
-                if (MODE == FQ_GRAM_SPLIT_BF16 || MODE == FQ_GRAM_SPLIT4_BF16) {
-                    const bf16x8 XL = __builtin_bit_cast(bf16x8, xl), YL = __builtin_bit_cast(bf16x8, yl);
-                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(XH, YL, acc, 0, 0, 0);
-                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(XL, YH, acc, 0, 0, 0);
-                    if (MODE == FQ_GRAM_SPLIT4_BF16) acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(XL, YL, acc, 0, 0, 0);
+            } else {
+                const int off = (lrow * LDB + lh * 32) * 2;   // bytes
+#pragma unroll
+                for (int q = 0; q < 32; q += 8) {
+                    uint4 hi, lo;
+                    split8(re + q, hi, lo);
+                    *reinterpret_cast<uint4*>(lds + 0 * PLANE + off + q * 2) = hi;
+                    *reinterpret_cast<uint4*>(lds + 1 * PLANE + off + q * 2) = lo;
+                    split8(im + q, hi, lo);
+                    *reinterpret_cast<uint4*>(lds + 2 * PLANE + off + q * 2) = hi;
+                    *reinterpret_cast<uint4*>(lds + 3 * PLANE + off + q * 2) = lo;
                 }
             }
         }
-        if ((stage + 1) % FLUSH == 0) {
+        __syncthreads();
+        if (lact && v0 + KC < v_end) load(v0 + KC);
+        if (!active) continue;
+        if (!SPLIT) {
+            const float* Re = reinterpret_cast<const float*>(lds);
+            const float* Im = reinterpret_cast<const float*>(lds + PLANE);
+            const int xo = (xrow + i) * LDW + h, yo = (yrow + i) * LDW + h;
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                acc64[r] += (double)acc[r];
-                acc[r] = 0.0f;
+            for (int kk = 0; kk < KC; kk += 2) {
+                const float xr = Re[xo + kk], xi = Im[xo + kk], yr = Re[yo + kk], yi = Im[yo + kk];
+                acc_re = __builtin_amdgcn_mfma_f32_32x32x2f32(xr, yr, acc_re, 0, 0, 0);
+                acc_re = __builtin_amdgcn_mfma_f32_32x32x2f32(xi, yi, acc_re, 0, 0, 0);
+                acc_im = __builtin_amdgcn_mfma_f32_32x32x2f32(xr, yi, acc_im, 0, 0, 0);
+                acc_im = __builtin_amdgcn_mfma_f32_32x32x2f32(-xi, yr, acc_im, 0, 0, 0);
             }
+        } else {
+            const int xo = ((xrow + i) * LDB + h * 8) * 2, yo = ((yrow + i) * LDB + h * 8) * 2;   // bytes
+#pragma unroll
+            for (int kk = 0; kk < KC; kk += 16) {
+                const int k2 = kk * 2;
+                const uint4 xrh = *reinterpret_cast<const uint4*>(lds + 0 * PLANE + xo + k2);
+                const uint4 xrl = *reinterpret_cast<const uint4*>(lds + 1 * PLANE + xo + k2);
+                const uint4 xih = *reinterpret_cast<const uint4*>(lds + 2 * PLANE + xo + k2);
+                const uint4 xil = *reinterpret_cast<const uint4*>(lds + 3 * PLANE + xo + k2);
+                const uint4 yrh = *reinterpret_cast<const uint4*>(lds + 0 * PLANE + yo + k2);
+                const uint4 yrl = *reinterpret_cast<const uint4*>(lds + 1 * PLANE + yo + k2);
+                const uint4 yih = *reinterpret_cast<const uint4*>(lds + 2 * PLANE + yo + k2);
+                const uint4 yil = *reinterpret_cast<const uint4*>(lds + 3 * PLANE + yo + k2);
+                // (x, y) operand pairs: Re.Re and Im.Im into Re G; Re.Im and (-Im).Re into Im G
+                const uint4 XH[4] = {xrh, xih, xrh, neg8(xih)}, XL[4] = {xrl, xil, xrl, neg8(xil)};
+                const uint4 YH[4] = {yrh, yih, yih, yrh}, YL[4] = {yrl, yil, yil, yrl};
+#pragma unroll
+                for (int p = 0; p < 4; ++p) {
+                    floatx16& acc = p < 2 ? acc_re : acc_im;
+                    const bf16x8 xh = __builtin_bit_cast(bf16x8, XH[p]), yh = __builtin_bit_cast(bf16x8, YH[p]);
+                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xh, yh, acc, 0, 0, 0);
+                    if (MODE == FQ_GRAM_SPLIT_BF16 || MODE == FQ_GRAM_SPLIT4_BF16) {
+                        const bf16x8 xl = __builtin_bit_cast(bf16x8, XL[p]), yl = __builtin_bit_cast(bf16x8, YL[p]);
+                        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xh, yl, acc, 0, 0, 0);
+                        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xl, yh, acc, 0, 0, 0);
+                        if (MODE == FQ_GRAM_SPLIT4_BF16) acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xl, yl, acc, 0, 0, 0);
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            sum_re[r] += (double)acc_re[r];
+            sum_im[r] += (double)acc_im[r];
+            acc_re[r] = acc_im[r] = 0.0f;
         }
     }
-#pragma unroll
-    for (int r = 0; r < 16; ++r) acc64[r] += (double)acc[r];
+    if (!active) return;
 
     // 32x32 accumulator layout: lane l holds column l%32, rows 8*(r/4) + 4*(l/32) + r%4
-    double* out = a.part + (((int64_t)split * a.ntiles + t) * 4 + w) * (GT * GT);
+    const int t = I * a.nb - I * (I - 1) / 2 + (J - I);
     const int col = l % 32;
+    double* out = a.part + ((int64_t)split * a.ntiles + t) * 2 * (GT * GT);
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
         const int row = 8 * (r / 4) + 4 * (l / 32) + (r % 4);
-        out[row * GT + col] = acc64[r];
+        out[row * GT + col] = sum_re[r];
+        out[GT * GT + row * GT + col] = sum_im[r];
     }
 }
 
@@ -198,66 +263,54 @@ __global__ void gram_reduce_kernel(const ReduceArgs a) {
     // tile index of (I, J) in the row-major upper triangle
     const int t = I * a.nb - I * (I - 1) / 2 + (J - I);
     const int i = lo % GT, j = hi % GT;
-    double rr = 0, ii = 0, ri = 0, ir = 0;
+    double re = 0.0, im = 0.0;
     for (int s = 0; s < a.nsplit; ++s) {
-        const double* p = a.part + ((int64_t)s * a.ntiles + t) * 4 * GT * GT + i * GT + j;
-        rr += p[0];
-        ii += p[GT * GT];
-        ri += p[2 * GT * GT];
-        ir += p[3 * GT * GT];
+        const double* p = a.part + ((int64_t)s * a.ntiles + t) * 2 * GT * GT + i * GT + j;
+        re += p[0];
+        im += p[GT * GT];
     }
-    double re = rr + ii, im = ri - ir;
     if (f == g) im = 0.0;
     if (f > g) im = -im;
     a.gram[idx] = make_double2(re, im);
 }
 
 struct Plan {
-    int nb, ntiles, nsplit;
+    int nb, ntiles, nbg, ngroups, nsplit;
     int64_t chunk;
     size_t bytes;
 };
 
-Plan plan(int64_t nv, int nt) {
+Plan plan(int64_t nv, int nt, size_t max_bytes = 0) {
     Plan p{};
     p.nb = (nt + GT - 1) / GT;
     p.ntiles = p.nb * (p.nb + 1) / 2;
+    p.nbg = (p.nb + GG - 1) / GG;
+    p.ngroups = p.nbg * (p.nbg + 1) / 2;
     // about 2048 workgroups; voxel ranges are whole multiples of the 4096-voxel block
-    int64_t want = std::max<int64_t>(1, 2048 / p.ntiles);
+    int64_t want = std::max<int64_t>(1, 2048 / p.ngroups);
+    if (max_bytes) {
+        // at most max_bytes of partial tiles: whole multiples of NXCD voxel ranges
+        const size_t per_split = (size_t)p.ntiles * 2 * GT * GT * sizeof(double);
+        const int64_t cap = (int64_t)(max_bytes / per_split) / NXCD * NXCD;
+        want = std::max<int64_t>(1, std::min<int64_t>(want, cap));
+    }
     int64_t chunk = (nv + want - 1) / want;
     chunk = std::max<int64_t>(4096, round_up((size_t)chunk, 4096));
     int64_t ns = (nv + chunk - 1) / chunk;
     p.nsplit = (int)round_up((size_t)ns, NXCD);
     p.chunk = chunk;
-    p.bytes = (size_t)p.nsplit * p.ntiles * 4 * GT * GT * sizeof(double);
+    p.bytes = (size_t)p.nsplit * p.ntiles * 2 * GT * GT * sizeof(double);
     return p;
 }
 
 }  // namespace
 }  // namespace fq
 
-using namespace fq;
+namespace fq {
+namespace {
 
-extern "C" size_t gram_workspace_size(int64_t n_vox, int32_t n_t, int32_t gram_mode) {
-    (void)gram_mode;
-    if (n_vox < 1 || n_t < 1) return 0;
-    return plan(n_vox, n_t).bytes;
-}
-
-extern "C" int casorati_gram(const float* iq, int64_t n_vox, int32_t n_t, int32_t gram_mode, void* ws, size_t ws_bytes,
-                             double* gram, void* stream) {
-    FQ_REQUIRE(n_t >= 1 && n_t <= FQ_MAX_NT, "n_t must be 1..%d", FQ_MAX_NT);
-    FQ_REQUIRE(n_vox >= 1, "n_vox must be >= 1");
-    FQ_REQUIRE(gram_mode == FQ_GRAM_FP32 || gram_mode == FQ_GRAM_SPLIT_BF16 || gram_mode == FQ_GRAM_BF16 ||
-                   gram_mode == FQ_GRAM_SPLIT4_BF16,
-               "bad gram_mode");
-    FQ_REQUIRE(iq && gram && ws && aligned16(iq) && aligned16(gram) && aligned16(ws), "null or misaligned pointer");
-    const Plan p = plan(n_vox, n_t);
-    if (ws_bytes < p.bytes) {
-        set_error("workspace too small: %zu < %zu bytes", ws_bytes, p.bytes);
-        return FQ_E_WORKSPACE;
-    }
-    hipStream_t s = as_stream(stream);
+int launch_gram(const float* iq, int64_t n_vox, int32_t n_t, int32_t gram_mode, const Plan& p, void* ws,
+                double* gram, hipStream_t s) {
     GramArgs ga{};
     ga.iq = reinterpret_cast<const float2*>(iq);
     ga.part = reinterpret_cast<double*>(ws);
@@ -267,7 +320,9 @@ extern "C" int casorati_gram(const float* iq, int64_t n_vox, int32_t n_t, int32_
     ga.nb = p.nb;
     ga.ntiles = p.ntiles;
     ga.nsplit = p.nsplit;
-    const unsigned nwg = (unsigned)(p.ntiles * p.nsplit);
+    ga.nbg = p.nbg;
+    ga.ngroups = p.ngroups;
+    const unsigned nwg = (unsigned)(p.ngroups * p.nsplit);
     switch (gram_mode) {
         case FQ_GRAM_FP32:
             hipLaunchKernelGGL(gram_kernel<FQ_GRAM_FP32>, dim3(nwg), dim3(GRAM_THREADS), 0, s, ga);
@@ -289,4 +344,37 @@ extern "C" int casorati_gram(const float* iq, int64_t n_vox, int32_t n_t, int32_
     hipLaunchKernelGGL(gram_reduce_kernel, dim3((n2 + 255) / 256), dim3(256), 0, s, ra);
     FQ_LAUNCH_CHECK();
     return FQ_OK;
+}
+
+int check_gram_args(const float* iq, int64_t n_vox, int32_t n_t, int32_t gram_mode, double* gram) {
+    FQ_REQUIRE(n_t >= 1 && n_t <= FQ_MAX_NT, "n_t must be 1..%d", FQ_MAX_NT);
+    FQ_REQUIRE(n_vox >= 1, "n_vox must be >= 1");
+    FQ_REQUIRE(gram_mode == FQ_GRAM_FP32 || gram_mode == FQ_GRAM_SPLIT_BF16 || gram_mode == FQ_GRAM_BF16 ||
+                   gram_mode == FQ_GRAM_SPLIT4_BF16,
+               "bad gram_mode");
+    FQ_REQUIRE(iq && gram && aligned16(iq) && aligned16(gram), "null or misaligned pointer");
+    return FQ_OK;
+}
+}  // namespace
+}  // namespace fq
+
+using namespace fq;
+
+extern "C" size_t gram_workspace_size(int64_t n_vox, int32_t n_t, int32_t gram_mode) {
+    (void)gram_mode;
+    if (n_vox < 1 || n_t < 1) return 0;
+    return plan(n_vox, n_t).bytes;
+}
+
+extern "C" int casorati_gram(const float* iq, int64_t n_vox, int32_t n_t, int32_t gram_mode, void* ws, size_t ws_bytes,
+                             double* gram, void* stream) {
+    int st = check_gram_args(iq, n_vox, n_t, gram_mode, gram);
+    if (st != FQ_OK) return st;
+    FQ_REQUIRE(ws && aligned16(ws), "null or misaligned workspace");
+    const Plan p = plan(n_vox, n_t);
+    if (ws_bytes < p.bytes) {
+        set_error("workspace too small: %zu < %zu bytes", ws_bytes, p.bytes);
+        return FQ_E_WORKSPACE;
+    }
+    return launch_gram(iq, n_vox, n_t, gram_mode, p, ws, gram, as_stream(stream));
 }

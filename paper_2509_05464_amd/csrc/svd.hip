@@ -1,18 +1,28 @@
 // svd_clutter_filter / hermitian_eig / power_doppler (gfx950).
 //
-// Eigendecomposition of the N_t x N_t Hermitian Gram G = S^H S in FP64, in four steps:
+// The clutter filter needs every eigenvalue of the N_t x N_t Hermitian Gram G = S^H S
+// (the singular-value curve, the knee) but only the K <= 64 leading eigenvectors (the
+// tissue subspace).  Its FP64 eigensolver therefore runs:
 //  1. tridiagonalisation (one workgroup): for k = 0 .. n-2 a Householder reflector
 //     H_k = I - tau_k v_k v_k^H (v_k[k+1] = 1) maps column k below the diagonal to
 //     beta_k e_1 with beta_k real, and the trailing block is updated two-sided,
 //     A22 <- H^H A22 H = A22 - (v w^H + w v^H),  w = tau A22 v - |tau|^2 (v^H A22 v) v / 2.
 //     G = Q T Q^H with Q = H_0 H_1 ... and T real symmetric tridiagonal (d, e = beta).
-//  2. implicit QL with Wilkinson shifts on T (one lane, on T scaled to unit size): the
-//     eigenvalues, plus the log of every plane rotation in the order applied;
-//  3. replay of the log on the identity, row by row (each lane owns a row of Z, held in
-//     LDS), which gives T = Z diag(lambda) Z^T; columns are ranked by descending eigenvalue;
-//  4. back-transformation of the wanted columns, V = Q Z, one wavefront per column.
-// Eigenvalues are clamped at zero (round-off of a PSD matrix), and the rank is chosen
-// (fixed, or the knee of the dB spectrum).
+//  2. eigenvalues of T by multisection on Sturm counts: the number of negative pivots of
+//     the LDL^T factorisation of T - x I is the number of eigenvalues below x (Sylvester's
+//     law of inertia); one wavefront per eigenvalue evaluates the count at 64 points of
+//     its bracket at once and keeps the sub-interval where the count passes the
+//     eigenvalue's index (a 65-fold narrowing per round), on T scaled to unit size;
+//  3. the rank K (fixed, or the knee of the dB spectrum);
+//  4. eigenvectors of T for the K leading eigenvalues by inverse iteration: a few solves
+//     of (T - lambda I) z = x with a tridiagonal LU factorisation with partial pivoting,
+//     one workgroup per eigenvalue, all in parallel; the vectors of eigenvalues closer
+//     than 1e-6 of ||T|| (a cluster) are then made orthogonal by Gram-Schmidt, twice;
+//  5. back-transformation of the K columns, V_K = Q Z_K, one wavefront per column.
+// hermitian_eig (every eigenvector) keeps the implicit QL iteration with Wilkinson shifts
+// (the EISPACK tql2 recurrence, Bowdler, Martin, Reinsch & Wilkinson 1968) on T, logging
+// each plane rotation, and replays the log on the identity to form all of Z.
+// Eigenvalues are clamped at zero (round-off of a PSD matrix).
 //
 // The projection S_f = S - (S V_K) V_K^H and the power Doppler are fused: one thread
 // per voxel reads its slow-time series twice (coalesced across voxels), first to form
@@ -31,6 +41,11 @@ constexpr int ROT_PER_N2 = 8;         // rotation log capacity, in units of n^2 
 // singular-value curve (Section 3.2) and power Doppler is shown over 60 dB (Sections 3.1,
 // 3.3); eigen-energies further below the leading one are treated as one flat floor.
 constexpr double KNEE_FLOOR = 1e-6;
+constexpr int EV_THREADS = 256;       // four eigenvalues (one per wavefront) per workgroup
+constexpr int EV_ROUNDS = 16;         // multisection rounds (65-fold narrowing each)
+constexpr double CLUSTER_TOL = 1e-6;  // eigenvalues of the unit-scaled T this close form a cluster
+constexpr int INVIT_ITERS = 4;        // inverse-iteration solves per eigenvector
+constexpr double DBL_TINY = 2.2250738585072014e-308;
 
 __device__ __forceinline__ double2 zmul(double2 a, double2 b) {
     return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
@@ -66,32 +81,48 @@ struct TriArgs {
     int n;
 };
 
+// The two-sided update of step k is applied lazily: step k+1 reads column k+1 through
+// it (for its reflector) and then makes one pass over its trailing block that applies
+// the update, stores the block and forms y = A22 v for its own reflector, so every step
+// reads and writes the trailing block once.  Each wavefront owns every 16th row of the
+// block (coalesced across columns, CT chunks of 64 columns per row) and loads its next
+// row before storing the current one.
+template <int CT>
 __global__ void __launch_bounds__(TRI_THREADS) tridiag_kernel(const TriArgs a) {
-    __shared__ double2 sv[FQ_MAX_NT], sy[FQ_MAX_NT];
+    __shared__ double2 pv[FQ_MAX_NT], pw[FQ_MAX_NT];   // v, w of the previous step (pending update)
+    __shared__ double2 sv[FQ_MAX_NT], sy[FQ_MAX_NT];   // v of this step; y = A22 v, then w
+    __shared__ double2 col[FQ_MAX_NT];                 // column k with the pending update applied
     __shared__ double red[TRI_THREADS / 64];
     __shared__ double2 s_tau, s_scale;
-    __shared__ int s_skip;
-    const int n = a.n, tid = threadIdx.x;
+    const int n = a.n, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    constexpr int NW = TRI_THREADS / 64;
     // Hermitian part of the input (the Gram is Hermitian up to its own rounding)
     for (int idx = tid; idx < n * n; idx += TRI_THREADS) {
         const int i = idx / n, j = idx - i * n;
         const double2 g = a.G[idx], gt = a.G[j * n + i];
         a.A[idx] = i == j ? make_double2(g.x, 0.0) : make_double2(0.5 * (g.x + gt.x), 0.5 * (g.y - gt.y));
     }
+    for (int i = tid; i < n; i += TRI_THREADS) {
+        pv[i] = make_double2(0.0, 0.0);
+        pw[i] = make_double2(0.0, 0.0);
+    }
     __syncthreads();
     for (int k = 0; k < n - 1; ++k) {
-        const int m = n - k - 1;            // length of the reflected part (rows k+1 .. n-1)
+        // column k (rows k .. n-1) with the previous step's update, read as the conjugate
+        // of row k (contiguous; A is kept Hermitian)
         double ps = 0.0;
-        for (int i = k + 2 + tid; i < n; i += TRI_THREADS) {
-            const double2 x = a.A[i * n + k];
-            ps += x.x * x.x + x.y * x.y;
+        for (int i = k + tid; i < n; i += TRI_THREADS) {
+            const double2 x0 = zconj(a.A[(size_t)k * n + i]);
+            const double2 p = zmulc(pv[i], pw[k]), q = zmulc(pw[i], pv[k]);
+            const double2 x = make_double2(x0.x - p.x - q.x, x0.y - p.y - q.y);
+            col[i] = x;
+            if (i >= k + 2) ps += x.x * x.x + x.y * x.y;
         }
         const double sigma = block_sum<TRI_THREADS>(ps, red);
         if (tid == 0) {
-            const double2 alpha = a.A[(k + 1) * n + k];
+            const double2 alpha = col[k + 1];
             double2 tau = make_double2(0.0, 0.0), scale = make_double2(0.0, 0.0);
             double beta = alpha.x;
-            int skip = 1;
             if (sigma > 0.0 || alpha.y != 0.0) {
                 const double nrm = sqrt(alpha.x * alpha.x + alpha.y * alpha.y + sigma);
                 beta = alpha.x >= 0.0 ? -nrm : nrm;
@@ -99,64 +130,81 @@ __global__ void __launch_bounds__(TRI_THREADS) tridiag_kernel(const TriArgs a) {
                 const double2 den = make_double2(alpha.x - beta, alpha.y);   // 1 / (alpha - beta)
                 const double dd = den.x * den.x + den.y * den.y;
                 scale = make_double2(den.x / dd, -den.y / dd);
-                skip = 0;
             }
             a.tau[k] = tau;
             a.e[k] = beta;
-            a.d[k] = a.A[k * n + k].x;
+            a.d[k] = col[k].x;
             s_tau = tau;
             s_scale = scale;
-            s_skip = skip;
         }
         __syncthreads();
         const double2 tau = s_tau, scale = s_scale;
-        const int skip = s_skip;
-        for (int i = tid; i < m; i += TRI_THREADS) {
-            const double2 v = i == 0 ? make_double2(1.0, 0.0) : zmul(a.A[(k + 1 + i) * n + k], scale);
+        for (int i = k + 1 + tid; i < n; i += TRI_THREADS) {
+            const double2 v = i == k + 1 ? make_double2(1.0, 0.0) : zmul(col[i], scale);
             sv[i] = v;
-            a.vh[k * n + k + 1 + i] = v;
+            a.vh[(size_t)k * n + i] = v;
         }
         __syncthreads();
-        if (skip) continue;
-        // y = A22 v, four threads per row
-        for (int row = tid >> 2; row < m; row += TRI_THREADS / 4) {
-            const double2* Ar = a.A + (size_t)(k + 1 + row) * n + (k + 1);
-            double2 acc = make_double2(0.0, 0.0);
-            for (int j = tid & 3; j < m; j += 4) {
-                const double2 x = Ar[j], v = sv[j];
-                acc.x += x.x * v.x - x.y * v.y;
-                acc.y += x.x * v.y + x.y * v.x;
+        // trailing block: apply the pending update, store, and y = A22 v; the wave's next
+        // row is loaded before the current one is stored (no store-to-load wait in the chain)
+        {
+            double2 cur[CT], nxt[CT];
+            int i = k + 1 + wv;
+#pragma unroll
+            for (int t = 0; t < CT; ++t) {
+                const int j = k + 1 + lane + 64 * t;
+                cur[t] = i < n && j < n ? a.A[(size_t)i * n + j] : make_double2(0.0, 0.0);
             }
-            acc.x += __shfl_xor(acc.x, 1);
-            acc.y += __shfl_xor(acc.y, 1);
-            acc.x += __shfl_xor(acc.x, 2);
-            acc.y += __shfl_xor(acc.y, 2);
-            if ((tid & 3) == 0) sy[row] = acc;
+            for (; i < n; i += NW) {
+                const int in = i + NW;
+#pragma unroll
+                for (int t = 0; t < CT; ++t) {
+                    const int j = k + 1 + lane + 64 * t;
+                    nxt[t] = in < n && j < n ? a.A[(size_t)in * n + j] : make_double2(0.0, 0.0);
+                }
+                double2* Ar = a.A + (size_t)i * n;
+                const double2 pvi = pv[i], pwi = pw[i];
+                double2 acc = make_double2(0.0, 0.0);
+#pragma unroll
+                for (int t = 0; t < CT; ++t) {
+                    const int j = k + 1 + lane + 64 * t;
+                    if (j < n) {
+                        const double2 x0 = cur[t];
+                        const double2 p = zmulc(pvi, pw[j]), q = zmulc(pwi, pv[j]);
+                        const double2 x = make_double2(x0.x - p.x - q.x, x0.y - p.y - q.y);
+                        Ar[j] = x;
+                        const double2 v = sv[j];
+                        acc.x += x.x * v.x - x.y * v.y;
+                        acc.y += x.x * v.y + x.y * v.x;
+                    }
+                    cur[t] = nxt[t];
+                }
+                for (int o = 32; o > 0; o >>= 1) {
+                    acc.x += __shfl_xor(acc.x, o);
+                    acc.y += __shfl_xor(acc.y, o);
+                }
+                if (lane == 0) sy[i] = acc;
+            }
         }
         __syncthreads();
-        // r = v^H y (real for Hermitian A22)
+        // r = v^H y (real for Hermitian A22); w = tau y - |tau|^2 r v / 2 becomes the pending update
         double pr = 0.0;
-        for (int i = tid; i < m; i += TRI_THREADS) pr += sv[i].x * sy[i].x + sv[i].y * sy[i].y;
+        for (int i = k + 1 + tid; i < n; i += TRI_THREADS) pr += sv[i].x * sy[i].x + sv[i].y * sy[i].y;
         const double r = block_sum<TRI_THREADS>(pr, red);
         const double hw = 0.5 * (tau.x * tau.x + tau.y * tau.y) * r;
-        for (int i = tid; i < m; i += TRI_THREADS) {
+        for (int i = k + 1 + tid; i < n; i += TRI_THREADS) {
             const double2 ty = zmul(tau, sy[i]);
-            sy[i] = make_double2(ty.x - hw * sv[i].x, ty.y - hw * sv[i].y);
-        }
-        __syncthreads();
-        // A22 -= v w^H + w v^H
-        for (int idx = tid; idx < m * m; idx += TRI_THREADS) {
-            const int i = idx / m, j = idx - i * m;
-            const double2 p = zmulc(sv[i], sy[j]), q = zmulc(sy[i], sv[j]);
-            double2* x = a.A + (size_t)(k + 1 + i) * n + (k + 1 + j);
-            const double2 o = *x;
-            *x = make_double2(o.x - p.x - q.x, o.y - p.y - q.y);
+            pv[i] = sv[i];
+            pw[i] = make_double2(ty.x - hw * sv[i].x, ty.y - hw * sv[i].y);
         }
         __syncthreads();
     }
     if (tid == 0) {
-        a.d[n - 1] = a.A[(n - 1) * n + (n - 1)].x;
-        a.e[n - 1] = 0.0;
+        const int m = n - 1;
+        const double2 x0 = a.A[(size_t)m * n + m];
+        const double2 p = zmulc(pv[m], pw[m]);
+        a.d[m] = x0.x - 2.0 * p.x;
+        a.e[m] = 0.0;
     }
 }
 
@@ -293,6 +341,300 @@ __global__ void __launch_bounds__(64) ql_kernel(const QlArgs a) {
     }
 }
 
+// ------------------------------------------------------------------ 2'. eigenvalues by multisection
+struct EigvalArgs {
+    const double* d;      // [n] diagonal of T
+    const double* e;      // [n] off-diagonal: e[i] couples i and i+1 (e[n-1] = 0)
+    double* ev;           // [n] eigenvalues of T / scale, descending, unclamped
+    double* scale;        // [1] the scale: infinity norm of T
+    double* lam;          // [n] eigenvalues of T, descending, clamped at 0
+    double* sigma;        // [n] sqrt(lam), or null
+    int* status;          // or null
+    int n;
+};
+
+// Number of eigenvalues of the scaled T below x: the negative pivots of the LDL^T
+// factorisation of T - x I.  A pivot smaller than pmin in magnitude is replaced by -pmin
+// (the count of a nearby matrix; no division by zero).
+__device__ __forceinline__ int sturm_count(const double* d, const double* e2, int n, double x, double pmin) {
+    double q = d[0] - x;
+    if (fabs(q) < pmin) q = -pmin;
+    int c = q < 0.0;
+    for (int i = 1; i < n; ++i) {
+        q = (d[i] - x) - e2[i - 1] / q;
+        if (fabs(q) < pmin) q = -pmin;
+        c += q < 0.0;
+    }
+    return c;
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+    return v;
+}
+__device__ __forceinline__ double wave_min(double v) {
+    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o));
+    return v;
+}
+__device__ __forceinline__ double wave_sum(double v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+__global__ void __launch_bounds__(EV_THREADS) eigval_kernel(const EigvalArgs a) {
+    constexpr int NW = EV_THREADS / 64;
+    __shared__ double sd[FQ_MAX_NT], se2[FQ_MAX_NT];
+    __shared__ double red[3][NW];
+    const int n = a.n, tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    // infinity norm of T
+    double nrm = 0.0;
+    for (int i = tid; i < n; i += EV_THREADS)
+        nrm = fmax(nrm, fabs(a.d[i]) + fabs(a.e[i]) + (i > 0 ? fabs(a.e[i - 1]) : 0.0));
+    nrm = wave_max(nrm);
+    if (lane == 0) red[0][w] = nrm;
+    __syncthreads();
+    double sc = 0.0;
+#pragma unroll
+    for (int k = 0; k < NW; ++k) sc = fmax(sc, red[0][k]);
+    const double isc = sc > 0.0 ? 1.0 / sc : 0.0;
+    // scaled T in LDS and its Gershgorin interval
+    double glo = 0.0, ghi = 0.0, emax = 0.0;
+    for (int i = tid; i < n; i += EV_THREADS) {
+        const double di = a.d[i] * isc, ei = i + 1 < n ? a.e[i] * isc : 0.0;
+        const double em = i > 0 ? a.e[i - 1] * isc : 0.0;
+        sd[i] = di;
+        se2[i] = ei * ei;
+        const double r = fabs(ei) + fabs(em);
+        glo = fmin(glo, di - r);
+        ghi = fmax(ghi, di + r);
+        emax = fmax(emax, ei * ei);
+    }
+    glo = wave_min(glo);
+    ghi = wave_max(ghi);
+    emax = wave_max(emax);
+    __syncthreads();
+    if (lane == 0) {
+        red[0][w] = glo;
+        red[1][w] = ghi;
+        red[2][w] = emax;
+    }
+    __syncthreads();
+    double gl = red[0][0], gu = red[1][0], e2max = red[2][0];
+#pragma unroll
+    for (int k = 1; k < NW; ++k) {
+        gl = fmin(gl, red[0][k]);
+        gu = fmax(gu, red[1][k]);
+        e2max = fmax(e2max, red[2][k]);
+    }
+    const double eps = 2.220446049250313e-16;
+    const double pmin = DBL_TINY * fmax(1.0, e2max);
+    const double widen = 2.1 * eps * n * fmax(fabs(gl), fabs(gu)) + 4.0 * pmin;
+    gl -= widen;
+    gu += widen;
+    if (blockIdx.x == 0 && tid == 0) {
+        *a.scale = sc;
+        if (a.status) *a.status = FQ_OK;
+    }
+    const int j = blockIdx.x * NW + w;   // index in ascending order
+    if (j >= n) return;
+    // bracket [lo, hi) with count(lo) <= j < count(hi), narrowed 65-fold per round
+    double lo = gl, hi = gu;
+    for (int r = 0; r < EV_ROUNDS; ++r) {
+        const double x = lo + (hi - lo) * ((double)(lane + 1) * (1.0 / 65.0));
+        const int c = sturm_count(sd, se2, n, x, pmin);
+        const uint64_t b = __ballot(c > j);
+        const int f = b ? __ffsll((unsigned long long)b) - 1 : 64;
+        const double xf = __shfl(x, f < 64 ? f : 63);
+        const double xp = __shfl(x, f > 0 ? f - 1 : 0);
+        if (f > 0) lo = xp;
+        if (f < 64) hi = xf;
+        if (hi - lo <= fmax(2.0 * eps * fmax(fabs(lo), fabs(hi)), 1e-20)) break;
+    }
+    if (lane == 0) {
+        const double ev = 0.5 * (lo + hi);
+        const int rk = n - 1 - j;
+        a.ev[rk] = ev;
+        const double l = ev > 0.0 ? ev * sc : 0.0;
+        a.lam[rk] = l;
+        if (a.sigma) a.sigma[rk] = sqrt(l);
+    }
+}
+
+// ------------------------------------------------------------------ 4'. inverse iteration
+struct InvitArgs {
+    const double* d;
+    const double* e;
+    const double* ev;       // [n] eigenvalues of T / scale, descending
+    const double* scale;    // [1]
+    const int* k_dev;       // vectors wanted (device word), or null: k_const
+    int k_const;
+    double* Z;              // [KMAX][n]: Z[j * n + i] = component i of the eigenvector of ev[j]
+    int* status;            // or null
+    int n;
+};
+
+// deterministic pseudo-random start vector in [-1, 1)
+__device__ __forceinline__ double start_component(int i, int j) {
+    uint32_t h = (uint32_t)i * 0x9E3779B1u ^ ((uint32_t)j * 0x85EBCA77u + 0x27D4EB2Fu);
+    h ^= h >> 15;
+    h *= 0x2C1B3C6Du;
+    h ^= h >> 12;
+    h *= 0x297A2D39u;
+    h ^= h >> 15;
+    return (double)h * (2.0 / 4294967296.0) - 1.0;
+}
+
+// One workgroup (one wavefront) per wanted eigenvalue.  T - lambda I is factorised by
+// Gaussian elimination with partial pivoting (rows i, i+1 exchanged when the sub-diagonal
+// entry is the larger): U has a diagonal, a super-diagonal and a second super-diagonal
+// (created by exchanges); pivots below eps of the unit-scaled T are raised to +-eps, which
+// is what makes the nearly singular solve amplify the wanted eigenvector.  The serial
+// factorisation and solves run on lane 0 with the next row's operands loaded one step
+// ahead (the dependent chain is then arithmetic only); normalisation is wave-parallel.
+// Vectors of eigenvalues closer than CLUSTER_TOL are made orthogonal afterwards
+// (orth_kernel); farther apart, inverse iteration leaves them orthogonal to ~eps/gap.
+__global__ void __launch_bounds__(64) invit_kernel(const InvitArgs a) {
+    __shared__ double sd[FQ_MAX_NT], se[FQ_MAX_NT];
+    __shared__ double ua[FQ_MAX_NT], ub[FQ_MAX_NT], uc[FQ_MAX_NT], lf[FQ_MAX_NT];
+    __shared__ unsigned char sw[FQ_MAX_NT];
+    __shared__ double x[FQ_MAX_NT];
+    const int n = a.n, lane = threadIdx.x, j = blockIdx.x;
+    const int K = a.k_dev ? *a.k_dev : a.k_const;
+    if (j >= K) return;
+    const double sc = *a.scale, isc = sc > 0.0 ? 1.0 / sc : 0.0;
+    const double lam = a.ev[j];
+    for (int i = lane; i < n; i += 64) {
+        sd[i] = a.d[i] * isc - lam;
+        se[i] = i + 1 < n ? a.e[i] * isc : 0.0;
+        x[i] = start_component(i, j);
+    }
+    __syncthreads();
+    const double tiny = 2.220446049250313e-16;
+    if (lane == 0) {
+        // elimination; (p, q) = diagonal and super-diagonal of the current row
+        double p = sd[0], q = se[0];
+        for (int i = 0; i + 1 < n; ++i) {
+            const double sub = se[i];                           // entry (i+1, i)
+            const double dn = sd[i + 1];                        // entry (i+1, i+1)
+            const double en = i + 2 < n ? se[i + 1] : 0.0;      // entry (i+1, i+2)
+            if (fabs(p) >= fabs(sub)) {
+                const double l = sub / (p != 0.0 ? p : tiny);
+                lf[i] = l;
+                sw[i] = 0;
+                ua[i] = p;
+                ub[i] = q;
+                uc[i] = 0.0;
+                p = dn - l * q;
+                q = en;
+            } else {
+                const double l = p / sub;
+                lf[i] = l;
+                sw[i] = 1;
+                ua[i] = sub;
+                ub[i] = dn;
+                uc[i] = en;
+                p = q - l * dn;
+                q = -l * en;
+            }
+        }
+        ua[n - 1] = p;
+        ub[n - 1] = 0.0;
+        uc[n - 1] = 0.0;
+    }
+    __syncthreads();
+    for (int i = lane; i < n; i += 64) {
+        const double p = ua[i];
+        ua[i] = 1.0 / (fabs(p) >= tiny ? p : (p < 0.0 ? -tiny : tiny));
+    }
+    __syncthreads();
+    int bad = 0;
+    for (int it = 0; it < INVIT_ITERS; ++it) {
+        if (lane == 0) {
+            // L y = P x: the carried value is x[i] as updated by step i-1
+            double c = x[0];
+            for (int i = 0; i + 1 < n; ++i) {
+                const double nx = x[i + 1];
+                const double l = lf[i];
+                if (sw[i]) {
+                    x[i] = nx;
+                    c = c - l * nx;
+                } else {
+                    x[i] = c;
+                    c = nx - l * c;
+                }
+            }
+            x[n - 1] = c;
+            // U z = y
+            double z1 = 0.0, z2 = 0.0;   // z[i+1], z[i+2]
+            for (int i = n - 1; i >= 0; --i) {
+                const double zi = (x[i] - ub[i] * z1 - uc[i] * z2) * ua[i];
+                x[i] = zi;
+                z2 = z1;
+                z1 = zi;
+            }
+        }
+        __syncthreads();
+        double ss = 0.0;
+        for (int i = lane; i < n; i += 64) ss += x[i] * x[i];
+        ss = wave_sum(ss);
+        const bool ok = ss > 0.0 && ss < 1.0 / 0.0;
+        bad |= !ok;
+        const double inv = ok ? 1.0 / sqrt(ss) : 0.0;
+        for (int i = lane; i < n; i += 64) x[i] = ok ? x[i] * inv : start_component(i, j + it + 1);
+        __syncthreads();
+    }
+    for (int i = lane; i < n; i += 64) a.Z[(size_t)j * n + i] = x[i];
+    if (bad && lane == 0 && a.status) *a.status = FQ_E_NUMERIC;
+}
+
+// Orthogonalisation inside clusters (one workgroup): for each wanted vector whose
+// eigenvalue lies within CLUSTER_TOL of the previous one, classical Gram-Schmidt against
+// the cluster's earlier vectors, applied twice, then normalisation.
+constexpr int ORTH_THREADS = 256;
+
+__global__ void __launch_bounds__(ORTH_THREADS) orth_kernel(const InvitArgs a) {
+    __shared__ double zj[FQ_MAX_NT];
+    __shared__ double dots[KMAX];
+    __shared__ double red[ORTH_THREADS / 64];
+    const int n = a.n, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int K = a.k_dev ? *a.k_dev : a.k_const;
+    int c = 0;   // first index of the current cluster
+    for (int j = 1; j < K; ++j) {
+        if (a.ev[j - 1] - a.ev[j] > CLUSTER_TOL) {
+            c = j;
+            continue;
+        }
+        double* z = a.Z + (size_t)j * n;
+        for (int i = tid; i < n; i += ORTH_THREADS) zj[i] = z[i];
+        __syncthreads();
+        for (int pass = 0; pass < 2; ++pass) {
+            for (int p = c + wv; p < j; p += ORTH_THREADS / 64) {
+                const double* zp = a.Z + (size_t)p * n;
+                double d = 0.0;
+                for (int i = lane; i < n; i += 64) d += zp[i] * zj[i];
+                d = wave_sum(d);
+                if (lane == 0) dots[p - c] = d;
+            }
+            __syncthreads();
+            for (int i = tid; i < n; i += ORTH_THREADS) {
+                double v = zj[i];
+                for (int p = c; p < j; ++p) v -= dots[p - c] * a.Z[(size_t)p * n + i];
+                zj[i] = v;
+            }
+            __syncthreads();
+        }
+        double ss = 0.0;
+        for (int i = tid; i < n; i += ORTH_THREADS) ss += zj[i] * zj[i];
+        ss = block_sum<ORTH_THREADS>(ss, red);
+        const bool ok = ss > 0.0 && ss < 1.0 / 0.0;
+        const double inv = ok ? 1.0 / sqrt(ss) : 0.0;
+        for (int i = tid; i < n; i += ORTH_THREADS) z[i] = zj[i] * inv;
+        if (!ok && tid == 0 && a.status) *a.status = FQ_E_NUMERIC;
+        __threadfence();   // the next vectors of the cluster read this one back
+        __syncthreads();
+    }
+}
+
 // ------------------------------------------------------------------ 3. replay of the log
 struct ReplayArgs {
     const int* rot_i;
@@ -371,10 +713,13 @@ __global__ void __launch_bounds__(64) replay_kernel(const ReplayArgs a) {
 
 // ------------------------------------------------------------------ 4. back-transformation
 struct BackArgs {
-    const double* Zs;     // [n][n]
+    const double* Z;      // eigenvectors of T: component i of vector j at Z[i * zr + j * zc]
+    int zr, zc;
     const double2* vh;    // [n][n]
     const double2* tau;   // [n]
-    double2* V;           // [n][n], columns 0 .. ncols-1 written
+    double2* V;           // [n][n], columns j < K written
+    const int* k_dev;     // K (device word), or null: k_const
+    int k_const;
     int n;
 };
 
@@ -382,11 +727,12 @@ constexpr int BT_PER_LANE = FQ_MAX_NT / 64;
 
 __global__ void __launch_bounds__(64) back_kernel(const BackArgs a) {
     const int n = a.n, j = blockIdx.x, lane = threadIdx.x;
+    if (j >= (a.k_dev ? *a.k_dev : a.k_const)) return;
     double2 z[BT_PER_LANE];
 #pragma unroll
     for (int t = 0; t < BT_PER_LANE; ++t) {
         const int i = lane + 64 * t;
-        z[t] = make_double2(i < n ? a.Zs[(size_t)i * n + j] : 0.0, 0.0);
+        z[t] = make_double2(i < n ? a.Z[(size_t)i * a.zr + (size_t)j * a.zc] : 0.0, 0.0);
     }
     for (int k = n - 2; k >= 0; --k) {
         const double2 tau = a.tau[k];
@@ -424,18 +770,15 @@ __global__ void __launch_bounds__(64) back_kernel(const BackArgs a) {
     }
 }
 
-// K selection and FP32 copy of V_K (one workgroup).
+// K selection (one thread).
 struct RankArgs {
     const double* lam;
-    const double2* vecs;   // [n][n]
-    float2* vk;            // [n][KMAX]
     int* k_used;
     int* status;           // may be null
     int n, cutoff;
 };
 
 __global__ void rank_kernel(const RankArgs a) {
-    __shared__ int Ks;
     const int n = a.n;
     if (threadIdx.x == 0) {
         int K;
@@ -467,19 +810,21 @@ __global__ void rank_kernel(const RankArgs a) {
                 if (a.status) *a.status = FQ_E_NUMERIC;
             }
         }
-        Ks = K;
         *a.k_used = K;
     }
-    __syncthreads();
-    const int K = Ks;
-    for (int idx = threadIdx.x; idx < n * KMAX; idx += blockDim.x) {
+}
+
+// FP32 copy of V_K, zero beyond column K (the projection runs whole size classes).
+__global__ void vk_kernel(const double2* vecs, const int* k_used, float2* vk, int n) {
+    const int K = *k_used;
+    for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < n * KMAX; idx += gridDim.x * blockDim.x) {
         const int f = idx / KMAX, k = idx % KMAX;
         float2 v = make_float2(0.f, 0.f);
         if (k < K) {
-            const double2 d = a.vecs[f * n + k];
+            const double2 d = vecs[(size_t)f * n + k];
             v = make_float2((float)d.x, (float)d.y);
         }
-        a.vk[idx] = v;
+        vk[idx] = v;
     }
 }
 
@@ -495,48 +840,141 @@ struct PdArgs {
     float inv_nt;
 };
 
-// The V_K copy (vk) is zero beyond column K, so every instantiation runs all KM columns
-// without a per-column test: the extra terms add exact zeros for finite data (a voxel
-// with a non-finite sample has a non-finite PD either way).  Frames are unrolled by 4 so
-// that several HBM loads of a voxel's series are in flight.
-template <int KM>
-__global__ void __launch_bounds__(256) project_pd_kernel(const PdArgs a) {
-    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (v >= a.nv) return;
+// Projection and power Doppler on the matrix cores.  A workgroup of four wavefronts
+// stages V_K (FP32 copy, zero beyond column K and frame n_t) in LDS once; each wavefront
+// then owns 16 voxels: P = S V_K (16 x KM) with v_mfma_f32_16x16x4_f32 over the frames
+// (the four real products of the complex product, S read straight from HBM as MFMA
+// operands), P staged in LDS, and R = S - P V_K^H formed 16 frames at a time with the
+// same MFMA over the K columns, subtracted from S (read again: the wavefront's 16-voxel
+// slice was just fetched, so this read is served by the L2), squared and summed per voxel.
+// MFMA 16x16x4 (FP32) lane layout: lane l supplies A[l%16][l/16] and B[l/16][l%16] and
+// holds D[4(l/16) + r][l%16], r = 0..3.
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+constexpr int PV = 16;             // voxels per wavefront
+constexpr int PW = 4;              // wavefronts per workgroup
+
+__host__ __device__ inline int vk_stride(int km) { return km + 2; }   // LDS row stride of V_K (float2)
+
+// VL: V_K staged in LDS (when it fits beside the P staging), else read from the
+// L2-resident table (rows beyond n_t are then masked).
+template <int KM, bool VL>
+__global__ void __launch_bounds__(64 * PW) project_mfma_kernel(const PdArgs a) {
+    extern __shared__ float2 sm2[];
     const int K = *a.k_used;
     if (K <= a.k_lo || K > KM) return;
-    float2 p[KM];
+    constexpr int NKT = KM / 16;
+    constexpr int VS = VL ? KM + 2 : KMAX;
+    constexpr int PS = KM + 1;
+    const int nt = a.nt, ntp = (nt + 15) & ~15;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    float* Pr = reinterpret_cast<float*>(sm2 + (VL ? ntp * VS : 0)) + wv * 2 * PV * PS;   // [PV][PS]
+    float* Pi = Pr + PV * PS;
+    if (VL) {
+        for (int idx = threadIdx.x; idx < ntp * KM; idx += 64 * PW) {
+            const int f = idx / KM, k = idx % KM;
+            sm2[f * VS + k] = f < nt ? a.vk[f * KMAX + k] : make_float2(0.f, 0.f);
+        }
+    }
+    const float2* V = VL ? sm2 : a.vk;   // [ntp or n_t][VS]
+    __syncthreads();
+    const int li = lane & 15, lk = lane >> 4;
+    const int64_t v0 = ((int64_t)blockIdx.x * PW + wv) * PV;
+    if (v0 >= a.nv) return;
+    const bool full = v0 + PV <= a.nv;
+    const float2* S = a.iq;
+    // P = S V_K: A[i][k] = S[voxel i][frame f0 + k], B[k][j] = V[frame f0 + k][column 16t + j]
+    floatx4 rr[NKT], ii[NKT], ri[NKT], ir[NKT];
 #pragma unroll
-    for (int k = 0; k < KM; ++k) p[k] = make_float2(0.f, 0.f);
-    if (K > 0) {
+    for (int t = 0; t < NKT; ++t)
+        for (int r = 0; r < 4; ++r) rr[t][r] = ii[t][r] = ri[t][r] = ir[t][r] = 0.f;
+    const bool vin = full || v0 + li < a.nv;
 #pragma unroll 4
-        for (int f = 0; f < a.nt; ++f) {
-            const float2 s = a.iq[(int64_t)f * a.nv + v];
-            const float2* vr = a.vk + f * KMAX;
+    for (int f0 = 0; f0 < ntp; f0 += 4) {
+        const int f = f0 + lk;
+        const float2 x = (f < nt && vin) ? S[(int64_t)f * a.nv + v0 + li] : make_float2(0.f, 0.f);
 #pragma unroll
-            for (int k = 0; k < KM; ++k) {
-                const float2 w = vr[k];
-                p[k].x = fmaf(s.x, w.x, fmaf(-s.y, w.y, p[k].x));
-                p[k].y = fmaf(s.x, w.y, fmaf(s.y, w.x, p[k].y));
+        for (int t = 0; t < NKT; ++t) {
+            const float2 w = (VL || f < nt) ? V[f * VS + 16 * t + li] : make_float2(0.f, 0.f);
+            rr[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(x.x, w.x, rr[t], 0, 0, 0);
+            ii[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(x.y, w.y, ii[t], 0, 0, 0);
+            ri[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(x.x, w.y, ri[t], 0, 0, 0);
+            ir[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(x.y, w.x, ir[t], 0, 0, 0);
+        }
+    }
+    // P[voxel 4 lk + r][column 16 t + li]
+#pragma unroll
+    for (int t = 0; t < NKT; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            Pr[(4 * lk + r) * PS + 16 * t + li] = rr[t][r] - ii[t][r];
+            Pi[(4 * lk + r) * PS + 16 * t + li] = ri[t][r] + ir[t][r];
+        }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    // R = S - P V_K^H, 16 frames at a time: A[i][k] = P[voxel i][k0 + k],
+    // B[k][j] = conj(V[frame f0 + j][k0 + k]); lane holds R[voxel 4 lk + r][frame f0 + li]
+    float pacc[4] = {0.f, 0.f, 0.f, 0.f};
+    for (int f0 = 0; f0 < ntp; f0 += 16) {
+        const int f = f0 + li;
+        floatx4 qa, qb, qc, qd;
+        for (int r = 0; r < 4; ++r) qa[r] = qb[r] = qc[r] = qd[r] = 0.f;
+#pragma unroll
+        for (int k0 = 0; k0 < KM; k0 += 4) {
+            const float pr = Pr[li * PS + k0 + lk], pi = Pi[li * PS + k0 + lk];
+            const float2 w = (VL || f < nt) ? V[f * VS + k0 + lk] : make_float2(0.f, 0.f);
+            qa = __builtin_amdgcn_mfma_f32_16x16x4f32(pr, w.x, qa, 0, 0, 0);
+            qb = __builtin_amdgcn_mfma_f32_16x16x4f32(pi, w.y, qb, 0, 0, 0);
+            qc = __builtin_amdgcn_mfma_f32_16x16x4f32(pi, w.x, qc, 0, 0, 0);
+            qd = __builtin_amdgcn_mfma_f32_16x16x4f32(pr, w.y, qd, 0, 0, 0);
+        }
+        float2 sv[4];
+        if (f < nt && full) {
+            const float4* sp = reinterpret_cast<const float4*>(S + (int64_t)f * a.nv + v0 + 4 * lk);
+            const float4 s0 = sp[0], s1 = sp[1];
+            sv[0] = make_float2(s0.x, s0.y);
+            sv[1] = make_float2(s0.z, s0.w);
+            sv[2] = make_float2(s1.x, s1.y);
+            sv[3] = make_float2(s1.z, s1.w);
+        } else {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t v = v0 + 4 * lk + r;
+                sv[r] = (f < nt && v < a.nv) ? S[(int64_t)f * a.nv + v] : make_float2(0.f, 0.f);
             }
         }
-    }
-    float acc = 0.f;
-#pragma unroll 4
-    for (int f = 0; f < a.nt; ++f) {
-        float2 r = a.iq[(int64_t)f * a.nv + v];
-        const float2* vr = a.vk + f * KMAX;
 #pragma unroll
-        for (int k = 0; k < KM; ++k) {
-            const float2 w = vr[k];   // subtract p_k conj(w)
-            r.x -= p[k].x * w.x + p[k].y * w.y;
-            r.y -= p[k].y * w.x - p[k].x * w.y;
+        for (int r = 0; r < 4; ++r) {
+            // P conj(V) = (Pr Vr + Pi Vi) + i (Pi Vr - Pr Vi)
+            const float xr = sv[r].x - (qa[r] + qb[r]);
+            const float xi = sv[r].y - (qc[r] - qd[r]);
+            pacc[r] = fmaf(xr, xr, fmaf(xi, xi, pacc[r]));
+            const int64_t v = v0 + 4 * lk + r;
+            if (a.out && f < nt && v < a.nv) a.out[(int64_t)f * a.nv + v] = make_float2(xr, xi);
         }
-        if (a.out) a.out[(int64_t)f * a.nv + v] = r;
-        acc = fmaf(r.x, r.x, fmaf(r.y, r.y, acc));
     }
-    if (a.pd) a.pd[v] = acc * a.inv_nt;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        float x = pacc[r];
+        for (int o = 1; o < 16; o <<= 1) x += __shfl_xor(x, o);
+        pacc[r] = x;
+    }
+    if (li == 0 && a.pd) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int64_t v = v0 + 4 * lk + r;
+            if (v < a.nv) a.pd[v] = pacc[r] * a.inv_nt;
+        }
+    }
 }
+
+constexpr size_t PROJ_LDS_MAX = 150 * 1024;
+
+size_t project_mfma_lds(int nt, int km, bool vl) {
+    const int ntp = (nt + 15) & ~15;
+    return (vl ? sizeof(float2) * (size_t)ntp * vk_stride(km) : 0) + sizeof(float) * 2 * PW * PV * (size_t)(km + 1);
+}
+bool project_vl(int nt, int km) { return project_mfma_lds(nt, km, true) <= PROJ_LDS_MAX; }
 
 __global__ void __launch_bounds__(256) pd_kernel(const float2* iq, int64_t nv, int nt, float inv_nt, float* pd) {
     const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -549,9 +987,15 @@ __global__ void __launch_bounds__(256) pd_kernel(const float2* iq, int64_t nv, i
     pd[v] = acc * inv_nt;
 }
 
+using TriFn = void (*)(const TriArgs);
+TriFn tri_fn(int n) {
+    if (n <= 256) return tridiag_kernel<4>;
+    return tridiag_kernel<FQ_MAX_NT / 64>;
+}
+
 struct SvdWs {
     size_t off_A, off_vh, off_tau, off_d, off_e, off_ri, off_rc, off_rs, off_rn, off_perm, off_Zs;
-    size_t off_lam, off_vecs, off_vk, off_k, total;
+    size_t off_lam, off_vecs, off_vk, off_k, off_ev, off_sc, off_zt, total;
     int cap;
 };
 
@@ -580,12 +1024,16 @@ SvdWs svd_layout(int n) {
     w.off_vecs = take(sizeof(double2) * nn);
     w.off_vk = take(sizeof(float2) * (size_t)n * KMAX);
     w.off_k = take(sizeof(int));
+    w.off_ev = take(sizeof(double) * n);
+    w.off_sc = take(sizeof(double));
+    w.off_zt = take(sizeof(double) * (size_t)n * KMAX);
     w.total = o;
     return w;
 }
 
-// Eigenvalues (descending, clamped) into lam/sigma; the leading ncols eigenvectors into
-// vecs ([n][n] complex128, columns in rank order) unless vecs is null.
+// Every eigenpair by QL (hermitian_eig): eigenvalues (descending, clamped) into lam/sigma;
+// the leading ncols eigenvectors into vecs ([n][n] complex128, columns in rank order)
+// unless vecs is null.
 int launch_eig(const double* gram, int n, char* ws, const SvdWs& L, double* lam, double* sigma, double* vecs,
                int ncols, int* status, hipStream_t s) {
     double2* vh = reinterpret_cast<double2*>(ws + L.off_vh);
@@ -600,7 +1048,7 @@ int launch_eig(const double* gram, int n, char* ws, const SvdWs& L, double* lam,
     double* Zs = reinterpret_cast<double*>(ws + L.off_Zs);
 
     TriArgs ta{reinterpret_cast<const double2*>(gram), reinterpret_cast<double2*>(ws + L.off_A), vh, tau, d, e, n};
-    hipLaunchKernelGGL(tridiag_kernel, dim3(1), dim3(TRI_THREADS), 0, s, ta);
+    hipLaunchKernelGGL(tri_fn(n), dim3(1), dim3(TRI_THREADS), 0, s, ta);
     FQ_LAUNCH_CHECK();
     QlArgs qa{d, e, ri, rc, rs, rn, L.cap, lam, sigma, perm, status, n};
     hipLaunchKernelGGL(ql_kernel, dim3(1), dim3(64), 0, s, qa);
@@ -610,19 +1058,56 @@ int launch_eig(const double* gram, int n, char* ws, const SvdWs& L, double* lam,
     ReplayArgs pa{ri, rc, rs, rn, perm, Zs, n, rows};
     hipLaunchKernelGGL(replay_kernel, dim3((n + rows - 1) / rows), dim3(64), sizeof(double) * (size_t)rows * n, s, pa);
     FQ_LAUNCH_CHECK();
-    BackArgs ba{Zs, vh, tau, reinterpret_cast<double2*>(vecs), n};
+    BackArgs ba{Zs, n, 1, vh, tau, reinterpret_cast<double2*>(vecs), nullptr, std::min(ncols, n), n};
     hipLaunchKernelGGL(back_kernel, dim3(std::min(ncols, n)), dim3(64), 0, s, ba);
     FQ_LAUNCH_CHECK();
     return FQ_OK;
 }
 
+// The clutter filter's eigensolver, first half: tridiagonalisation and every eigenvalue
+// (lam, sigma, and the unit-scaled ev for the vectors).
+int launch_eigvals(const double* gram, int n, char* ws, const SvdWs& L, double* lam, double* sigma, int* status,
+                   hipStream_t s) {
+    TriArgs ta{reinterpret_cast<const double2*>(gram), reinterpret_cast<double2*>(ws + L.off_A),
+               reinterpret_cast<double2*>(ws + L.off_vh), reinterpret_cast<double2*>(ws + L.off_tau),
+               reinterpret_cast<double*>(ws + L.off_d), reinterpret_cast<double*>(ws + L.off_e), n};
+    hipLaunchKernelGGL(tri_fn(n), dim3(1), dim3(TRI_THREADS), 0, s, ta);
+    FQ_LAUNCH_CHECK();
+    EigvalArgs ea{reinterpret_cast<const double*>(ws + L.off_d), reinterpret_cast<const double*>(ws + L.off_e),
+                  reinterpret_cast<double*>(ws + L.off_ev), reinterpret_cast<double*>(ws + L.off_sc), lam, sigma,
+                  status, n};
+    constexpr int per_block = EV_THREADS / 64;
+    hipLaunchKernelGGL(eigval_kernel, dim3((n + per_block - 1) / per_block), dim3(EV_THREADS), 0, s, ea);
+    FQ_LAUNCH_CHECK();
+    return FQ_OK;
+}
+
+// Second half: the K leading eigenvectors (K from the device word k_dev, else k_const),
+// by inverse iteration on T and back-transformation, into vecs columns 0 .. K-1.
+int launch_eigvecs(int n, char* ws, const SvdWs& L, const int* k_dev, int k_const, double* vecs, int* status,
+                   hipStream_t s) {
+    double* zt = reinterpret_cast<double*>(ws + L.off_zt);
+    const int grid = k_dev ? KMAX : k_const;
+    if (grid < 1) return FQ_OK;
+    InvitArgs ia{reinterpret_cast<const double*>(ws + L.off_d), reinterpret_cast<const double*>(ws + L.off_e),
+                 reinterpret_cast<const double*>(ws + L.off_ev), reinterpret_cast<const double*>(ws + L.off_sc),
+                 k_dev, k_const, zt, status, n};
+    hipLaunchKernelGGL(invit_kernel, dim3(grid), dim3(64), 0, s, ia);
+    FQ_LAUNCH_CHECK();
+    hipLaunchKernelGGL(orth_kernel, dim3(1), dim3(ORTH_THREADS), 0, s, ia);
+    FQ_LAUNCH_CHECK();
+    BackArgs ba{zt, 1, n, reinterpret_cast<const double2*>(ws + L.off_vh),
+                reinterpret_cast<const double2*>(ws + L.off_tau), reinterpret_cast<double2*>(vecs), k_dev, k_const, n};
+    hipLaunchKernelGGL(back_kernel, dim3(grid), dim3(64), 0, s, ba);
+    FQ_LAUNCH_CHECK();
+    return FQ_OK;
+}
+
 using PdFn = void (*)(const PdArgs);
-PdFn pd_fn(int k) {
-    if (k <= 4) return project_pd_kernel<4>;
-    if (k <= 8) return project_pd_kernel<8>;
-    if (k <= 16) return project_pd_kernel<16>;
-    if (k <= 32) return project_pd_kernel<32>;
-    return project_pd_kernel<64>;
+PdFn pd_fn(int k, bool vl) {
+    if (k <= 16) return vl ? project_mfma_kernel<16, true> : project_mfma_kernel<16, false>;
+    if (k <= 32) return vl ? project_mfma_kernel<32, true> : project_mfma_kernel<32, false>;
+    return vl ? project_mfma_kernel<64, true> : project_mfma_kernel<64, false>;
 }
 
 }  // namespace
@@ -668,16 +1153,27 @@ extern "C" int svd_clutter_filter(const float* iq, int64_t n_vox, int32_t n_t, c
     char* w = reinterpret_cast<char*>(ws);
     double* lam = reinterpret_cast<double*>(w + L.off_lam);
     double* vecs = reinterpret_cast<double*>(w + L.off_vecs);
-    int st = launch_eig(gram, n_t, w, L, lam, sigma, vecs, std::min(n_t, KMAX), status, s);
+    int st = launch_eigvals(gram, n_t, w, L, lam, sigma, status, s);
     if (st != FQ_OK) return st;
+    RankArgs ra{lam, k_used, status, n_t, cutoff};
     if (cutoff == FQ_CUTOFF_SSM) {
-        // the leading min(n_t, 64) eigenvectors are the ones back-transformed above
-        st = launch_ssm(iq, n_vox, n_t, vecs, std::min(n_t, FQ_SSM_MAX_MODES), w + L.total, nullptr, k_used, s);
+        // the rank is read from the leading min(n_t, 64) spatial modes
+        const int M = std::min(n_t, FQ_SSM_MAX_MODES);
+        st = launch_eigvecs(n_t, w, L, nullptr, M, vecs, status, s);
+        if (st != FQ_OK) return st;
+        st = launch_ssm(iq, n_vox, n_t, vecs, M, w + L.total, nullptr, k_used, s);
+        if (st != FQ_OK) return st;
+        hipLaunchKernelGGL(rank_kernel, dim3(1), dim3(64), 0, s, ra);
+        FQ_LAUNCH_CHECK();
+    } else {
+        hipLaunchKernelGGL(rank_kernel, dim3(1), dim3(64), 0, s, ra);
+        FQ_LAUNCH_CHECK();
+        st = launch_eigvecs(n_t, w, L, k_used, 0, vecs, status, s);
         if (st != FQ_OK) return st;
     }
-    RankArgs ra{lam, reinterpret_cast<const double2*>(vecs), reinterpret_cast<float2*>(w + L.off_vk), k_used, status,
-                n_t, cutoff};
-    hipLaunchKernelGGL(rank_kernel, dim3(1), dim3(256), 0, s, ra);
+    hipLaunchKernelGGL(vk_kernel, dim3((n_t * KMAX + 255) / 256), dim3(256), 0, s,
+                       reinterpret_cast<const double2*>(vecs), static_cast<const int*>(k_used),
+                       reinterpret_cast<float2*>(w + L.off_vk), n_t);
     FQ_LAUNCH_CHECK();
     if (!iq_filt && !pd) return FQ_OK;
     PdArgs pa{};
@@ -689,18 +1185,22 @@ extern "C" int svd_clutter_filter(const float* iq, int64_t n_vox, int32_t n_t, c
     pa.nv = n_vox;
     pa.nt = n_t;
     pa.inv_nt = 1.0f / (float)n_t;
-    const unsigned blocks = (unsigned)((n_vox + 255) / 256);
+    const unsigned blocks = (unsigned)((n_vox + PV * PW - 1) / (PV * PW));
     if (cutoff >= 0) {
+        const int km = cutoff <= 16 ? 16 : (cutoff <= 32 ? 32 : 64);
         pa.k_lo = -1;
-        hipLaunchKernelGGL(pd_fn(cutoff), dim3(blocks), dim3(256), 0, s, pa);
+        const bool vl = project_vl(n_t, km);
+        hipLaunchKernelGGL(pd_fn(km, vl), dim3(blocks), dim3(64 * PW), project_mfma_lds(n_t, km, vl), s, pa);
         FQ_LAUNCH_CHECK();
     } else {
         // the knee's K is only known on the device: every size class is launched and
         // all but the one holding K return at once
-        const int bounds[6] = {-1, 4, 8, 16, 32, 64};
-        for (int c = 0; c < 5; ++c) {
+        const int bounds[4] = {-1, 16, 32, 64};
+        for (int c = 0; c < 3; ++c) {
             pa.k_lo = bounds[c];
-            hipLaunchKernelGGL(pd_fn(bounds[c + 1]), dim3(blocks), dim3(256), 0, s, pa);
+            const bool vl = project_vl(n_t, bounds[c + 1]);
+            hipLaunchKernelGGL(pd_fn(bounds[c + 1], vl), dim3(blocks), dim3(64 * PW),
+                               project_mfma_lds(n_t, bounds[c + 1], vl), s, pa);
             FQ_LAUNCH_CHECK();
         }
     }

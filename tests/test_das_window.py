@@ -1,0 +1,112 @@
+"""The beamformer's on-chip delay window holds every tap it reads (host check, no GPU).
+
+For one 16 x 16 x 4-voxel tile and one (transmit, element) the kernel stages W delay
+rows starting at n_lo = floor(tx_min + rx_min) - 2, where tx_min is the transmit delay at
+the tile corner that the plane wave reaches first and rx_min the receive distance to the
+tile point nearest the element (both in samples).  A voxel's taps start at row
+    n_tx + n_rx + floor(f_tx + k dxz + f_rx) - n_lo + j0,
+(n_tx, f_tx: integer and FP32 fractional transmit delay of the thread's first voxel; k
+the voxel's step down the column; dxz the transmit delay per z step; n_rx, f_rx the
+receive delay; j0 = 0 linear, -1 cubic) and span NT = 2 or 4 rows.  This test evaluates
+that arithmetic exactly as the kernel does (FP64 geometry, FP32 fractions) for the
+corner voxels of every tile, which bound the whole tile (the transmit delay is linear
+and the receive distance convex in the voxel position), for a set of elements that
+includes the array's corners, with W from the library's own host query, and checks
+0 <= row <= W - NT.  Geometries: the workloads' grids and transmits, and extreme tilts."""
+import math
+
+import numpy as np
+import pytest
+
+from fqscene import get_config
+
+TILE_X, TILE_Y, VZ = 16, 16, 4
+
+
+def _rows(acq, tilts_rad, elems, W):
+    fs_c = acq.fs / acq.c
+    fc_fs = acq.fc / acq.fs
+    nx_el, ny_el = acq.nx_el, acq.ny_el
+    ex = ((elems % nx_el) - 0.5 * (nx_el - 1)) * acq.pitch
+    ey = ((elems // nx_el) - 0.5 * (ny_el - 1)) * acq.pitch
+    hx, hy = 0.5 * (nx_el - 1) * acq.pitch, 0.5 * (ny_el - 1) * acq.pitch
+    ntx_t = -(-acq.nx // TILE_X)
+    nty_t = -(-acq.ny // TILE_Y)
+    ntz_t = -(-acq.nz // VZ)
+    tz, ty, tx = np.meshgrid(np.arange(ntz_t), np.arange(nty_t), np.arange(ntx_t), indexing='ij')
+    tx, ty, tz = tx.ravel(), ty.ravel(), tz.ravel()
+    bx0 = acq.x0 + tx * TILE_X * acq.dx
+    by0 = acq.y0 + ty * TILE_Y * acq.dy
+    bz0 = acq.z0 + tz * VZ * acq.dz
+    bx1 = bx0 + (TILE_X - 1) * acq.dx
+    by1 = by0 + (TILE_Y - 1) * acq.dy
+    lo, hi = np.inf, -np.inf
+    for (thx, thy) in tilts_rad:
+        sx, sy = math.sin(thx), math.sin(thy)
+        ux, uy, uz = sx, sy, math.sqrt(1.0 - sx * sx - sy * sy)
+        t0s = (-abs(sx) * hx - abs(sy) * hy) / acq.c * acq.fs
+        dxz = np.float32(uz * acq.dz * fs_c)
+        tmin = (ux * np.where(ux > 0, bx0, bx1) + uy * np.where(uy > 0, by0, by1) + uz * bz0) * fs_c - t0s
+        for pex, pey in zip(ex, ey):
+            cx = np.clip(pex, bx0, bx1) - pex
+            cy = np.clip(pey, by0, by1) - pey
+            rmin = np.sqrt(cx * cx + cy * cy + bz0 * bz0) * fs_c
+            nlo = np.floor(tmin + rmin).astype(np.int64) - 2
+            for lx in (0, TILE_X - 1):
+                for ly in (0, TILE_Y - 1):
+                    xv = bx0 + lx * acq.dx
+                    yv = by0 + ly * acq.dy
+                    xt = (ux * xv + uy * yv + uz * bz0) * fs_c - t0s
+                    ntx = np.floor(xt)
+                    ftx = (xt - ntx).astype(np.float32)
+                    dxy2 = (xv - pex) ** 2 + (yv - pey) ** 2
+                    for k in (0, VZ - 1):
+                        z = bz0 + k * acq.dz
+                        xr = np.sqrt(dxy2 + z * z) * fs_c
+                        nrx = np.floor(xr)
+                        frx = (xr - nrx).astype(np.float32)
+                        s = (ftx + np.float32(k) * dxz + frx).astype(np.float32)
+                        row = ntx.astype(np.int64) + nrx.astype(np.int64) + np.floor(s).astype(np.int64) - nlo
+                        lo = min(lo, int(row.min()))
+                        hi = max(hi, int(row.max()))
+    return lo, hi
+
+
+def _elements(acq, n_extra, seed):
+    E = acq.n_elem
+    corners = [0, acq.nx_el - 1, E - acq.nx_el, E - 1, E // 2 + acq.nx_el // 2]
+    rng = np.random.default_rng(seed)
+    return np.unique(np.concatenate([corners, rng.integers(0, E, n_extra)])).astype(np.int64)
+
+
+EXTREME = ((math.radians(35.0), math.radians(30.0)), (math.radians(-35.0), math.radians(-30.0)),
+           (math.radians(40.0), 0.0), (0.0, math.radians(-40.0)), (0.0, 0.0))
+
+
+@pytest.mark.parametrize('name,tilts', [('c1', None), ('c2', None), ('c5', None), ('p7', None),
+                                        ('c2', EXTREME), ('p7', EXTREME), ('c1', EXTREME)])
+def test_every_tap_lies_in_the_staged_window(name, tilts):
+    import paper_2509_05464_amd as fq
+    acq = get_config(name).acq
+    if tilts is None:
+        tilts = acq.tilts_rad()
+    probe = fq.make_probe(acq.nx_el, acq.ny_el, acq.pitch, acq.pitch, acq.fc, acq.fs, acq.c)
+    tx = fq.make_tx(tilts)
+    grid = fq.make_grid(acq.nx, acq.ny, acq.nz, acq.x0, acq.y0, acq.z0, acq.dx, acq.dy, acq.dz)
+    W = fq.das_window_rows(probe, tx, grid)
+    elems = _elements(acq, 12, 7)
+    lo, hi = _rows(acq, tilts, elems, W)
+    # linear taps: rows [row, row + 1]; cubic taps: [row - 1, row + 2]
+    print(name, 'W', W, 'first tap row', lo, 'last tap row', hi)
+    assert lo - 1 >= 0, (lo, W)
+    assert hi + 2 <= W - 1, (hi, W)
+
+
+def test_window_query_rejects_bad_arguments():
+    import paper_2509_05464_amd as fq
+    acq = get_config('c1').acq
+    probe = fq.make_probe(acq.nx_el, acq.ny_el, acq.pitch, acq.pitch, acq.fc, acq.fs, acq.c)
+    tx = fq.make_tx(acq.tilts_rad())
+    bad = fq.make_grid(0, 1, 1, 0.0, 0.0, 1e-3, 1e-4, 1e-4, 1e-4)
+    with pytest.raises(fq.FqError):
+        fq.das_window_rows(probe, tx, bad)
