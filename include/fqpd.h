@@ -43,6 +43,7 @@ extern "C" {
 #define FQ_MAX_ANGLES 32
 #define FQ_MAX_NT 512
 #define FQ_SSM_MAX_MODES 64
+#define FQ_GRAM_SCRATCH_BYTES (48u << 20)   /* static scratch of casorati_gram_noalloc, per GPU */
 
 enum { FQ_OK = 0, FQ_E_INVALID = 1, FQ_E_WORKSPACE = 2, FQ_E_HIP = 3, FQ_E_NUMERIC = 4 };
 enum { FQ_INTERP_LINEAR = 0, FQ_INTERP_HERMITE = 1 };
@@ -213,6 +214,24 @@ int das_window_rows(const fq_probe* probe, const fq_tx* tx, const fq_grid* grid)
 size_t gram_workspace_size(int64_t n_vox, int32_t n_t, int32_t gram_mode);
 int casorati_gram(const float* iq, int64_t n_vox, int32_t n_t, int32_t gram_mode, void* ws,
                   size_t ws_bytes, double* gram, void* stream);
+
+/* casorati_gram_noalloc -- casorati_gram for callers that cannot allocate device memory
+ * (work recorded under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): no workspace argument and no allocation of any kind; the partial tiles
+ * live in a static device array of FQ_GRAM_SCRATCH_BYTES (48 MiB) that the library holds on
+ * each GPU it runs on until the process ends (its address is looked up on the first call
+ * on a device).  Same arguments, arithmetic and result as casorati_gram, except that the
+ * voxel range is split into fewer parts when the partial tiles would not fit, so the
+ * FP64 sums can differ from casorati_gram's in the last bits.  The array holds at least
+ * 8 voxel ranges of partial tiles (FP64, 2 x 32 x 32 per tile: Re G, Im G) for every n_t
+ * up to FQ_MAX_NT (136 tiles at n_t = 512: 17.8 MB).
+ * Every call on a GPU shares that GPU's array and leaves it holding its partial tiles:
+ * calls that overlap on one GPU (different streams, or threads) race and must be
+ * serialised by the caller.
+ *  Errors: as casorati_gram (FQ_E_INVALID also when n_t needs more scratch than the
+ *  array holds); FQ_E_HIP if the array's device address cannot be looked up. */
+int casorati_gram_noalloc(const float* iq, int64_t n_vox, int32_t n_t, int32_t gram_mode,
+                          double* gram, void* stream);
 
 /* ---------------------------------------------------------------------------------
  * svd_clutter_filter -- eigendecomposition of G in FP64 on the GPU (Householder

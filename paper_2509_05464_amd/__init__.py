@@ -11,7 +11,7 @@ from ._lib import (  # noqa: F401
     GRAM_FP32, GRAM_SPLIT_BF16, GRAM_BF16, GRAM_SPLIT4_BF16, INTERP_LINEAR, INTERP_HERMITE,
     Probe, Tx, Grid, Pulse, FdParams, make_probe, make_tx, make_grid, make_pulse, make_fd_params, lib,
     fd_workspace_size, fd_synth,
-    rf_synth, das_workspace_size, das_window_rows, das_beamform, das_demodulate, das_delay_sum, gram_workspace_size, casorati_gram,
+    rf_synth, das_workspace_size, das_window_rows, das_beamform, das_demodulate, das_delay_sum, gram_workspace_size, casorati_gram, casorati_gram_noalloc,
     svd_workspace_size, svd_clutter_filter, hermitian_eig, power_doppler, ssm_workspace_size, spatial_similarity,
     display_workspace_size, display_db, mip, image_quality,
     lcf_act_size, lcf_forward, lcf_backward, lcf_adam_step, lcf_gather,

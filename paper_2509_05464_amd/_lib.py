@@ -114,6 +114,7 @@ _SIGS = {
     'das_window_rows': (ctypes.c_int, [_P(Probe), _P(Tx), _P(Grid)]),
     'gram_workspace_size': (_sz, [_i64, _i32, _i32]),
     'casorati_gram': (ctypes.c_int, [_vp, _i64, _i32, _i32, _vp, _sz, _vp, _vp]),
+    'casorati_gram_noalloc': (ctypes.c_int, [_vp, _i64, _i32, _i32, _vp, _vp]),
     'svd_workspace_size': (_sz, [_i64, _i32]),
     'svd_clutter_filter': (ctypes.c_int, [_vp, _i64, _i32, _vp, _i32, _vp, _sz, _vp, _vp, _vp, _vp, _vp, _vp]),
     'hermitian_eig': (ctypes.c_int, [_vp, _i32, _vp, _sz, _vp, _vp, _vp, _vp]),
@@ -274,6 +275,13 @@ def roof_probe(which: int, out: torch.Tensor, iters: int) -> None:
     n_blocks = out.numel() // 256
     st = lib().roof_probe(which, n_blocks, iters, _ptr(out), _stream())
     _check('roof_probe', st)
+
+
+def casorati_gram_noalloc(iq: torch.Tensor, gram: torch.Tensor, mode: int = GRAM_FP32) -> None:
+    """casorati_gram without a workspace (the library's static scratch array)."""
+    nt, nv = iq.shape
+    st = lib().casorati_gram_noalloc(_ptr(_f32view(iq)), nv, nt, mode, _ptr(_f32view(gram)), _stream())
+    _check('casorati_gram_noalloc', st)
 
 
 def svd_workspace_size(n_vox: int, n_t: int) -> int:

@@ -23,6 +23,8 @@
 // order (deterministic).
 // Workgroups that share a voxel range are placed on the same XCD so the range is read
 // from HBM once and served to the other groups from that XCD's L2.
+#include <mutex>
+
 #include "fq_common.hpp"
 
 namespace fq {
@@ -306,8 +308,31 @@ Plan plan(int64_t nv, int nt, size_t max_bytes = 0) {
 }  // namespace
 }  // namespace fq
 
+// Partial tiles of casorati_gram_noalloc: a static device array (each GPU the library runs
+// on holds its own copy until the process ends).  Host code never passes the symbol
+// itself to a kernel: its device address is looked up once per device.
+static __device__ __align__(256) unsigned char scratch[FQ_GRAM_SCRATCH_BYTES];
+
 namespace fq {
 namespace {
+constexpr int MAX_DEVICES = 64;
+void* g_scratch_ptr[MAX_DEVICES];
+std::mutex g_scratch_mu;
+
+int scratch_for_current_device(void** out) {
+    int dev = -1;
+    FQ_HIP(hipGetDevice(&dev));
+    FQ_REQUIRE(dev >= 0 && dev < MAX_DEVICES, "device ordinal %d out of range", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        FQ_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        FQ_REQUIRE(ptr != nullptr, "no device address for the Gram scratch array");
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return FQ_OK;
+}
 
 int launch_gram(const float* iq, int64_t n_vox, int32_t n_t, int32_t gram_mode, const Plan& p, void* ws,
                 double* gram, hipStream_t s) {
@@ -359,6 +384,21 @@ int check_gram_args(const float* iq, int64_t n_vox, int32_t n_t, int32_t gram_mo
 }  // namespace fq
 
 using namespace fq;
+
+extern "C" int casorati_gram_noalloc(const float* iq, int64_t n_vox, int32_t n_t, int32_t gram_mode, double* gram,
+                                     void* stream) {
+    int st = check_gram_args(iq, n_vox, n_t, gram_mode, gram);
+    if (st != FQ_OK) return st;
+    const Plan p = plan(n_vox, n_t, FQ_GRAM_SCRATCH_BYTES);
+    if (p.bytes > FQ_GRAM_SCRATCH_BYTES) {
+        set_error("n_t = %d needs %zu bytes of partial tiles, above the %zu-byte static scratch", n_t, p.bytes,
+                  (size_t)FQ_GRAM_SCRATCH_BYTES);
+        return FQ_E_INVALID;
+    }
+    void* ws = nullptr;
+    if ((st = scratch_for_current_device(&ws)) != FQ_OK) return st;
+    return launch_gram(iq, n_vox, n_t, gram_mode, p, ws, gram, as_stream(stream));
+}
 
 extern "C" size_t gram_workspace_size(int64_t n_vox, int32_t n_t, int32_t gram_mode) {
     (void)gram_mode;
