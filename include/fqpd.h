@@ -186,7 +186,7 @@ int das_delay_sum(const fq_probe* probe, const fq_tx* tx, const fq_grid* grid, i
                   void* stream);
 
 /* Host-only query (no device work): the delay rows per (transmit, element) that
- * das_delay_sum stages on chip for one 16 x 16 x 4-voxel tile.  The bound is the
+ * das_delay_sum stages on chip for one 16 x 16 x 2-voxel tile.  The bound is the
  * tile's diameter (receive distances are 1-Lipschitz in the voxel position) plus the
  * transmit-plane spread over the tile, in samples, plus 8 rows of margin for the
  * interpolation taps and the integer/fraction splits, rounded up to a multiple of 8.

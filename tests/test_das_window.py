@@ -1,6 +1,6 @@
 """The beamformer's on-chip delay window holds every tap it reads (host check, no GPU).
 
-For one 16 x 16 x 4-voxel tile and one (transmit, element) the kernel stages W delay
+For one 16 x 16 x 2-voxel tile and one (transmit, element) the kernel stages W delay
 rows starting at n_lo = floor(tx_min + rx_min) - 2, where tx_min is the transmit delay at
 the tile corner that the plane wave reaches first and rx_min the receive distance to the
 tile point nearest the element (both in samples).  A voxel's taps start at row
@@ -20,7 +20,7 @@ import pytest
 
 from fqscene import get_config
 
-TILE_X, TILE_Y, VZ = 16, 16, 4
+TILE_X, TILE_Y, VZ = 16, 16, 2
 
 
 def _rows(acq, tilts_rad, elems, W):
