@@ -32,9 +32,8 @@ typedef unsigned short u16x4 __attribute__((ext_vector_type(4)));
 constexpr int CH = 32, KW = 9, PADT = 4;
 constexpr int OFF_W1 = 0, OFF_B1 = 576, OFF_W2 = 608, OFF_B2 = 9824, OFF_W3 = 9856, OFF_B3 = 19072,
               OFF_W4 = 19104, OFF_B4 = 19168, NPAR = 19170;
-constexpr int K1C = 5;    // layer-1 K chunks: 9 taps x 8 channel slots = 72 -> 80
+constexpr int K1C = 2;    // layer-1 K chunks: 9 taps x 2 channels = 18 -> 32
 constexpr int K2C = 18;   // 32->32 K chunks: 9 taps x 32 channels = 288
-constexpr int GS = 4;     // series staged together (coalesced loads)
 constexpr int NWB = 256;  // waves of the backward reduction kernels
 constexpr int PART = 9216 + 32;   // partial gradient of one 32->32 layer (W then b)
 constexpr int PART1 = 576 + 32;   // partial gradient of layer 1
@@ -48,18 +47,19 @@ __device__ __forceinline__ unsigned short f2bf(float x) {
 __device__ __forceinline__ float bf2f(unsigned short b) { return __uint_as_float((unsigned int)b << 16); }
 __device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
 // GELU for the forward pass, whose result is rounded to BF16: erf by formula 7.1.26 of
-// Abramowitz & Stegun (Handbook of Mathematical Functions), |error| <= 1.5e-7, i.e.
-// erf(x) = 1 - t (a1 + t (a2 + t (a3 + t (a4 + t a5)))) exp(-x^2), t = 1/(1 + p x), x >= 0.
+// Abramowitz & Stegun (Handbook of Mathematical Functions), |error| <= 1.5e-7,
+//   1 - erf(x) = t (a1 + t (a2 + t (a3 + t (a4 + t a5)))) exp(-x^2), t = 1/(1 + p x), x >= 0,
+// at x = |z|/sqrt 2.  With q = (1 - erf(x))/2 (the a_i halved),
+//   GELU(z) = z (1 + sign(z) erf(x))/2 = max(z, 0) - |z| q.
 __device__ __forceinline__ float gelu_fwd(float z) {
-    const float x = fabsf(z) * 0.70710678118654752f;
-    const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f, x, 1.0f));
-    float poly = fmaf(1.061405429f, t, -1.453152027f);
-    poly = fmaf(poly, t, 1.421413741f);
-    poly = fmaf(poly, t, -0.284496736f);
-    poly = fmaf(poly, t, 0.254829592f);
-    const float q = poly * t * __builtin_amdgcn_exp2f(-1.4426950408889634f * x * x);   // 1 - erf(x)
-    // GELU = z (1 + sign(z) erf(|z|/sqrt 2)) / 2
-    return z >= 0.0f ? fmaf(-0.5f * z, q, z) : 0.5f * z * q;
+    const float az = fabsf(z);
+    const float t = __builtin_amdgcn_rcpf(fmaf(0.23164189f, az, 1.0f));   // p / sqrt 2
+    float poly = fmaf(0.5307027145f, t, -0.7265760135f);
+    poly = fmaf(poly, t, 0.7107068705f);
+    poly = fmaf(poly, t, -0.142248368f);
+    poly = fmaf(poly, t, 0.127414796f);
+    const float e = __builtin_amdgcn_exp2f((z * -0.72134752044448170f) * z);   // exp(-z^2 / 2)
+    return fmaf(-az, poly * t * e, fmaxf(z, 0.0f));
 }
 // two floats to BF16 (round to nearest even) with the hardware pair conversion
 __device__ __forceinline__ unsigned int f2bf2(float lo, float hi) {
@@ -102,15 +102,6 @@ __device__ void frag_fwd32(const uint16_t* wb, int base, int l, u16x8* fr) {
         for (int q = 0; q < 8; ++q) fr[c][q] = wb[base + o * 288 + (i0 + q) * 9 + k];
     }
 }
-__device__ void frag_fwd1(const uint16_t* wb, int l, u16x8* fr) {
-    const int o = l % 32, h = l / 32;
-#pragma unroll
-    for (int c = 0; c < K1C; ++c) {
-        const int k = 2 * c + h;
-#pragma unroll
-        for (int q = 0; q < 8; ++q) fr[c][q] = (q < 2 && k < KW) ? wb[OFF_W1 + o * 18 + q * 9 + k] : (unsigned short)0;
-    }
-}
 // dgrad: A[i][k'*32 + o] = W[o][i][8 - k']
 __device__ void frag_dgrad32(const uint16_t* wb, int base, int l, u16x8* fr) {
     const int i = l % 32, h = l / 32;
@@ -136,21 +127,6 @@ __device__ __forceinline__ floatx16 conv32(const unsigned short* img, int t0, co
     }
     return acc;
 }
-// the input layer: 8-channel image (channels 0, 1 used)
-__device__ __forceinline__ floatx16 conv8(const unsigned short* img, int t0, const u16x8* fr, int l) {
-    const int j = l % 32, h = l / 32;
-    floatx16 acc;
-#pragma unroll
-    for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
-#pragma unroll
-    for (int c = 0; c < K1C; ++c) {
-        const int k = 2 * c + h;
-        const u16x8 b = *reinterpret_cast<const u16x8*>(img + (t0 + j + k) * 8);
-        acc = mfma(fr[c], b, acc);
-    }
-    return acc;
-}
-
 // 32x32 accumulator layout: lane l holds frame column l%32 and channel rows
 // 8*(r/4) + 4*(l/32) + r%4, r = 0..15 (four groups of four consecutive channels).
 __device__ __forceinline__ int acc_row(int r, int l) { return 8 * (r / 4) + 4 * (l / 32) + (r % 4); }
@@ -168,124 +144,229 @@ struct FwdArgs {
     float eps;
 };
 
-__global__ void __launch_bounds__(64) lcf_fwd_kernel(const FwdArgs a) {
+// An FP32 bias enters the products exactly as three BF16 terms (hi + mid + lo = b: each
+// split leaves a remainder with 8 fewer significant bits), each times a B entry of 1.
+__device__ __forceinline__ void split3(float b, unsigned short* o) {
+    o[0] = f2bf(b);
+    const float r1 = b - bf2f(o[0]);
+    o[1] = f2bf(r1);
+    o[2] = f2bf(r1 - bf2f(o[1]));
+}
+constexpr unsigned int BF_ONE2 = 0x3F803F80u;   // two BF16 ones
+// Row stride (elements) of the forward pass's 32-channel image: 80 bytes, so the 16-byte
+// reads of consecutive rows by consecutive lanes fall in distinct banks (a 64-byte stride
+// puts every other row, or every fourth, on the same banks).
+constexpr int RS = 40;
+
+// input layer: kk = 2k + i (tap-major over the 2 input channels), 18 used of 32; the bias
+// terms sit at kk = 18, 19, 20 (chunk 1, lanes h = 0, elements 2..4)
+__device__ void frag_fwd1(const uint16_t* wb, const float* w, int l, u16x8* fr) {
+    const int o = l % 32, h = l / 32;
+#pragma unroll
+    for (int c = 0; c < K1C; ++c) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int kk = 16 * c + 8 * h + q, k = kk / 2, i = kk % 2;
+            fr[c][q] = k < KW ? wb[OFF_W1 + o * 18 + i * 9 + k] : (unsigned short)0;
+        }
+    }
+    unsigned short bs[3];
+    split3(w[OFF_B1 + o], bs);
+    if (h == 0) {
+        fr[1][2] = bs[0];
+        fr[1][3] = bs[1];
+        fr[1][4] = bs[2];
+    }
+}
+// bias chunk of a 32->32 layer (kk = 288..290, lanes h = 0)
+__device__ u16x8 frag_bias(const float* w, int off, int l) {
+    u16x8 fr;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) fr[q] = 0;
+    unsigned short bs[3];
+    split3(w[off + l % 32], bs);
+    if (l < 32) {
+        fr[0] = bs[0];
+        fr[1] = bs[1];
+        fr[2] = bs[2];
+    }
+    return fr;
+}
+// output layer as a 32-row product (rows 0, 1 used) over the 32 channels of h3 in the
+// order the layer-3 accumulator holds them: chunk c, element e is channel
+// 8 (2c + e/4) + 4h + e%4
+__device__ void frag_out(const uint16_t* wb, int l, u16x8* fr) {
+    const int o = l % 32, h = l / 32;
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int ch = 8 * (2 * c + e / 4) + 4 * h + e % 4;
+            fr[c][e] = o < 2 ? wb[OFF_W4 + o * CH + ch] : (unsigned short)0;
+        }
+    }
+}
+
+// the input layer's conv: 2-channel image, 4 bytes per row; a lane's 8 consecutive kk are
+// taps 8c + 4h .. 8c + 4h + 3 of both channels, 16 contiguous bytes (4-byte aligned)
+__device__ __forceinline__ floatx16 conv2(const unsigned short* img, int t0, const u16x8* fr, int l) {
+    const int j = l % 32, h = l / 32;
+    const unsigned int* im = reinterpret_cast<const unsigned int*>(img);
+    floatx16 acc;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
+#pragma unroll
+    for (int c = 0; c < K1C; ++c) {
+        const int row = t0 + j + 8 * c + 4 * h;
+        uint4 w = make_uint4(im[row], im[row + 1], im[row + 2], im[row + 3]);
+        if (c == 1 && h == 0) w.y = w.z = BF_ONE2;   // B = 1 against the bias terms
+        acc = mfma(fr[c], __builtin_bit_cast(u16x8, w), acc);
+    }
+    return acc;
+}
+// a 32->32 conv tile with its bias chunk
+__device__ __forceinline__ floatx16 conv32b(const unsigned short* img, int t0, const u16x8* fr, const u16x8& fb,
+                                           int l) {
+    const int j = l % 32, h = l / 32;
+    u16x8 one;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) one[q] = q < 3 ? (unsigned short)0x3F80 : (unsigned short)0;
+    floatx16 acc;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
+    acc = mfma(fb, one, acc);
+#pragma unroll
+    for (int c = 0; c < K2C; ++c) {
+        const int k = c / 2, ch0 = (c % 2) * 16 + 8 * h;
+        const u16x8 b = *reinterpret_cast<const u16x8*>(img + (t0 + j + k) * RS + ch0);
+        acc = mfma(fr[c], b, acc);
+    }
+    return acc;
+}
+
+// GELU of one 32x32 output tile (this lane: frame t, channels 8q + 4h + p), rounded to
+// BF16 (zero for frames past the end: they are the next layer's padding).  With an
+// activation record, z and h of the layer are stored too.
+template <bool ACT>
+__device__ __forceinline__ void gelu_tile(const floatx16& acc, uint16_t* actv, int layer, int t, int T, int h,
+                                          uint2* hv) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const float z[4] = {acc[4 * q], acc[4 * q + 1], acc[4 * q + 2], acc[4 * q + 3]};
+        hv[q] = t < T ? make_uint2(f2bf2(gelu_fwd(z[0]), gelu_fwd(z[1])), f2bf2(gelu_fwd(z[2]), gelu_fwd(z[3])))
+                      : make_uint2(0u, 0u);
+        if (ACT && actv) {
+            const int o = 8 * q + 4 * h;
+            *reinterpret_cast<uint2*>(actv + act_off(2 * layer - 1, T) + t * CH + o) =
+                make_uint2(f2bf2(z[0], z[1]), f2bf2(z[2], z[3]));
+            *reinterpret_cast<uint2*>(actv + act_off(2 * layer, T) + t * CH + o) = hv[q];
+        }
+    }
+}
+
+// One wave per series at a time (grid-stride), two waves per SIMD: one wave's GELU
+// epilogue overlaps the other's matrix products.  Every layer, biases and the output
+// layer included, runs on the matrix cores; the weights stay in registers as MFMA
+// fragments.  The next series' samples are fetched into registers (XR per lane, frames
+// l, l+64, ...) while the current one is processed.
+template <int XR, bool ACT>
+__global__ void __launch_bounds__(64, 2) lcf_fwd_kernel(const FwdArgs a) {
     extern __shared__ float4 smem4[];
     const Geo g(a.T);
     const int l = threadIdx.x;
-    float* par = reinterpret_cast<float*>(smem4);                 // b1 b2 b3 (96) w4 (64) b4 (2) -> 176
-    float2* xs = reinterpret_cast<float2*>(par + 176);             // [GS][T]
-    unsigned short* h0 = reinterpret_cast<unsigned short*>(xs + GS * g.T);   // [TP+1][8]
-    unsigned short* ha = h0 + (g.TP + 1) * 8;                                // [TP][32]
-    unsigned short* hb = ha + g.TP * CH;                                     // [TP][32]
+    unsigned short* h0 = reinterpret_cast<unsigned short*>(smem4);   // [TP+8][2]
+    unsigned short* hb = h0 + (g.TP + 8) * 2;                        // [TP][RS], layers 1 and 2
 
-    u16x8 f1[K1C], f2[K2C], f3[K2C];
-    frag_fwd1(a.wb, l, f1);
+    u16x8 f1[K1C], f2[K2C], f3[K2C], f4[2];
+    frag_fwd1(a.wb, a.w, l, f1);
     frag_fwd32(a.wb, OFF_W2, l, f2);
     frag_fwd32(a.wb, OFF_W3, l, f3);
-    for (int i = l; i < 176; i += 64) {
-        float v;
-        if (i < 32) v = a.w[OFF_B1 + i];
-        else if (i < 64) v = a.w[OFF_B2 + i - 32];
-        else if (i < 96) v = a.w[OFF_B3 + i - 64];
-        else if (i < 160) v = bf2f(a.wb[OFF_W4 + i - 96]);
-        else if (i < 162) v = a.w[OFF_B4 + i - 160];
-        else v = 0.0f;
-        par[i] = v;
-    }
-    for (int i = l; i < (g.TP + 1) * 8 + 2 * g.TP * CH; i += 64) h0[i] = 0;   // padding rows stay zero
+    frag_out(a.wb, l, f4);
+    const u16x8 fb2 = frag_bias(a.w, OFF_B2, l), fb3 = frag_bias(a.w, OFF_B3, l);
+    const float b40 = a.w[OFF_B4], b41 = a.w[OFF_B4 + 1];
+    for (int i = l; i < (g.TP + 8) * 2 + g.TP * RS; i += 64) h0[i] = 0;   // padding rows stay zero
     __builtin_amdgcn_wave_barrier();
 
     const int h = l / 32, j = l % 32;
-    for (int64_t v0 = (int64_t)blockIdx.x * GS; v0 < a.N; v0 += (int64_t)gridDim.x * GS) {
-        const int ns = (int)min<int64_t>(GS, a.N - v0);
-        for (int i = l; i < GS * g.T; i += 64) {
-            const int t = i / GS, s = i % GS;
-            xs[s * g.T + t] = s < ns ? a.x[(int64_t)t * a.N + v0 + s] : make_float2(0.f, 0.f);
+    float2 xn[XR];
+    auto fetch = [&](int64_t v) {
+#pragma unroll
+        for (int q = 0; q < XR; ++q) {
+            const int t = l + 64 * q;
+            xn[q] = (v < a.N && t < g.T) ? a.x[(int64_t)t * a.N + v] : make_float2(0.f, 0.f);
+        }
+    };
+    fetch(blockIdx.x);
+    for (int64_t v = blockIdx.x; v < a.N; v += gridDim.x) {
+        float2 xc[XR];
+#pragma unroll
+        for (int q = 0; q < XR; ++q) xc[q] = xn[q];
+        fetch(v + gridDim.x);
+        float ss = 0.0f;
+#pragma unroll
+        for (int q = 0; q < XR; ++q) ss += xc[q].x * xc[q].x + xc[q].y * xc[q].y;
+        const float r = sqrtf(wave_sum(ss) / (float)g.T + a.eps);
+        const float ir = 1.0f / r;
+        uint16_t* actv = ACT ? a.act + v * act_stride(g.T) : nullptr;
+#pragma unroll
+        for (int q = 0; q < XR; ++q) {
+            const int t = l + 64 * q;
+            if (t < g.T) {
+                const unsigned int p = f2bf2(xc[q].x * ir, xc[q].y * ir);
+                *reinterpret_cast<unsigned int*>(h0 + (t + PADT) * 2) = p;
+                if (ACT) *reinterpret_cast<unsigned int*>(actv + act_off(0, g.T) + 2 * t) = p;
+            }
         }
         __builtin_amdgcn_wave_barrier();
-        for (int s = 0; s < ns; ++s) {
-            const int64_t v = v0 + s;
-            const float2* xv = xs + s * g.T;
-            float ss = 0.0f;
-            for (int t = l; t < g.T; t += 64) ss += xv[t].x * xv[t].x + xv[t].y * xv[t].y;
-            const float r = sqrtf(wave_sum(ss) / (float)g.T + a.eps);
-            const float ir = 1.0f / r;
-            uint16_t* actv = a.act ? a.act + v * act_stride(g.T) : nullptr;
-            for (int t = l; t < g.T; t += 64) {
-                const unsigned short re = f2bf(xv[t].x * ir), im = f2bf(xv[t].y * ir);
-                h0[(t + PADT) * 8] = re;
-                h0[(t + PADT) * 8 + 1] = im;
-                if (actv) {
-                    actv[act_off(0, g.T) + 2 * t] = re;
-                    actv[act_off(0, g.T) + 2 * t + 1] = im;
-                }
-            }
-            __builtin_amdgcn_wave_barrier();
-            // layer 1 -> ha ; layer 2 -> hb
-            for (int layer = 1; layer <= 2; ++layer) {
-                unsigned short* dst = layer == 1 ? ha : hb;
-                const float* bias = par + (layer - 1) * 32;
-                for (int tt = 0; tt < g.TT; ++tt) {
-                    const floatx16 acc = layer == 1 ? conv8(h0, 32 * tt, f1, l) : conv32(ha, 32 * tt, f2, l);
-                    const int t = 32 * tt + j;
-                    const bool live = t < g.T;
+        // layer 1 -> hb; layer 2 -> hb in place: the output of a 32-frame tile is stored
+        // only after the next tile's products have read their inputs (the taps reach 4
+        // frames into the neighbouring tiles), so one image serves both layers
+        for (int tt = 0; tt < g.TT; ++tt) {
+            const floatx16 acc = conv2(h0, 32 * tt, f1, l);
+            const int t = 32 * tt + j;
+            uint2 hv[4];
+            gelu_tile<ACT>(acc, t < g.T ? actv : nullptr, 1, t, g.T, h, hv);
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        const int o = 8 * q + 4 * h;
-                        float z[4];
-#pragma unroll
-                        for (int p = 0; p < 4; ++p) z[p] = acc[4 * q + p] + bias[o + p];
-                        uint2 hv = make_uint2(f2bf2(gelu_fwd(z[0]), gelu_fwd(z[1])), f2bf2(gelu_fwd(z[2]), gelu_fwd(z[3])));
-                        if (!live) hv = make_uint2(0u, 0u);
-                        *reinterpret_cast<uint2*>(dst + (t + PADT) * CH + o) = hv;
-                        if (actv && live) {
-                            const uint2 zv = make_uint2(f2bf2(z[0], z[1]), f2bf2(z[2], z[3]));
-                            *reinterpret_cast<uint2*>(actv + act_off(2 * layer - 1, g.T) + t * CH + o) = zv;
-                            *reinterpret_cast<uint2*>(actv + act_off(2 * layer, g.T) + t * CH + o) = hv;
-                        }
-                    }
-                }
-                __builtin_amdgcn_wave_barrier();
-            }
-            // layer 3 + output layer
-            float pdacc = 0.0f;
-            for (int tt = 0; tt < g.TT; ++tt) {
-                const floatx16 acc = conv32(hb, 32 * tt, f3, l);
-                const int t = 32 * tt + j;
-                float y0 = 0.0f, y1 = 0.0f;
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int o = 8 * q + 4 * h;
-                    float z[4];
-#pragma unroll
-                    for (int p = 0; p < 4; ++p) z[p] = acc[4 * q + p] + par[64 + o + p];
-                    const uint2 hv = make_uint2(f2bf2(gelu_fwd(z[0]), gelu_fwd(z[1])), f2bf2(gelu_fwd(z[2]), gelu_fwd(z[3])));
-                    const float hf[4] = {__uint_as_float(hv.x << 16), __uint_as_float(hv.x & 0xffff0000u),
-                                         __uint_as_float(hv.y << 16), __uint_as_float(hv.y & 0xffff0000u)};
-#pragma unroll
-                    for (int p = 0; p < 4; ++p) {
-                        y0 = fmaf(par[96 + o + p], hf[p], y0);
-                        y1 = fmaf(par[128 + o + p], hf[p], y1);
-                    }
-                    if (actv && t < g.T) {
-                        const uint2 zv = make_uint2(f2bf2(z[0], z[1]), f2bf2(z[2], z[3]));
-                        *reinterpret_cast<uint2*>(actv + act_off(5, g.T) + t * CH + o) = zv;
-                        *reinterpret_cast<uint2*>(actv + act_off(6, g.T) + t * CH + o) = hv;
-                    }
-                }
-                y0 += __shfl_xor(y0, 32);
-                y1 += __shfl_xor(y1, 32);
-                y0 += par[160];
-                y1 += par[161];
-                if (h == 0 && t < g.T) {
-                    pdacc += y0 * y0 + y1 * y1;
-                    if (a.y) a.y[(int64_t)t * a.N + v] = make_float2(r * y0, r * y1);
-                }
-            }
-            pdacc = wave_sum(pdacc);
-            if (a.pd && l == 0) a.pd[v] = r * r * pdacc / (float)g.T;
-            __builtin_amdgcn_wave_barrier();
+            for (int q = 0; q < 4; ++q) *reinterpret_cast<uint2*>(hb + (t + PADT) * RS + 8 * q + 4 * h) = hv[q];
         }
+        __builtin_amdgcn_wave_barrier();
+        uint2 pend[4];
+        for (int tt = 0; tt < g.TT; ++tt) {
+            const floatx16 acc = conv32b(hb, 32 * tt, f2, fb2, l);
+            if (tt > 0) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    *reinterpret_cast<uint2*>(hb + (32 * tt - 32 + j + PADT) * RS + 8 * q + 4 * h) = pend[q];
+            }
+            const int t = 32 * tt + j;
+            gelu_tile<ACT>(acc, t < g.T ? actv : nullptr, 2, t, g.T, h, pend);
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            *reinterpret_cast<uint2*>(hb + (32 * g.TT - 32 + j + PADT) * RS + 8 * q + 4 * h) = pend[q];
+        __builtin_amdgcn_wave_barrier();
+        // layer 3 and the output layer: y = W4 h3 (rows 0 and 1 of a 32-row product whose
+        // B operand is h3 as this lane already holds it) + b4
+        float pdacc = 0.0f;
+        for (int tt = 0; tt < g.TT; ++tt) {
+            const floatx16 acc = conv32b(hb, 32 * tt, f3, fb3, l);
+            const int t = 32 * tt + j;
+            uint2 hv[4];
+            gelu_tile<ACT>(acc, t < g.T ? actv : nullptr, 3, t, g.T, h, hv);
+            floatx16 yo;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) yo[r] = 0.0f;
+            yo = mfma(f4[0], __builtin_bit_cast(u16x8, make_uint4(hv[0].x, hv[0].y, hv[1].x, hv[1].y)), yo);
+            yo = mfma(f4[1], __builtin_bit_cast(u16x8, make_uint4(hv[2].x, hv[2].y, hv[3].x, hv[3].y)), yo);
+            if (h == 0 && t < g.T) {   // rows 0 and 1 of column j
+                const float y0 = yo[0] + b40, y1 = yo[1] + b41;
+                pdacc += y0 * y0 + y1 * y1;
+                if (a.y) a.y[(int64_t)t * a.N + v] = make_float2(r * y0, r * y1);
+            }
+        }
+        pdacc = wave_sum(pdacc);
+        if (a.pd && l == 0) a.pd[v] = r * r * pdacc / (float)g.T;
+        __builtin_amdgcn_wave_barrier();
     }
 }
 
@@ -640,7 +721,7 @@ constexpr int FB_BLOCKS = 512;
 
 size_t fwd_lds(int T) {
     const int TP = 32 * ((T + 31) / 32) + 8;
-    return 176 * 4 + (size_t)GS * T * 8 + (size_t)(TP + 1) * 8 * 2 + 2 * (size_t)TP * CH * 2;
+    return (size_t)(TP + 8) * 2 * 2 + (size_t)TP * RS * 2;
 }
 size_t bwd_lds(int T) {
     const int TP = 32 * ((T + 31) / 32) + 8;
@@ -672,9 +753,10 @@ extern "C" int lcf_forward(const float* w, const uint16_t* w_bf16, const float* 
     const size_t lds = fwd_lds(n_t);
     FQ_REQUIRE(lds <= 160 * 1024, "n_t too large");
     FwdArgs fa{w, w_bf16, reinterpret_cast<const float2*>(x), act, reinterpret_cast<float2*>(y), pd, n_series, n_t, eps};
-    const int64_t groups = (n_series + GS - 1) / GS;
-    const unsigned grid = (unsigned)std::min<int64_t>(groups, 8192);
-    hipLaunchKernelGGL(lcf_fwd_kernel, dim3(grid), dim3(64), lds, as_stream(stream), fa);
+    const unsigned grid = (unsigned)std::min<int64_t>(n_series, 8192);
+    auto kern = n_t <= 256 ? (act ? lcf_fwd_kernel<4, true> : lcf_fwd_kernel<4, false>)
+                           : (act ? lcf_fwd_kernel<8, true> : lcf_fwd_kernel<8, false>);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(64), lds, as_stream(stream), fa);
     FQ_LAUNCH_CHECK();
     return FQ_OK;
 }
