@@ -61,24 +61,18 @@ __device__ __forceinline__ void tile_ij(int t, int nb, int& I, int& J) {
     J = i + t;
 }
 
-__device__ __forceinline__ unsigned short bf16_rne_bits(float x) {
-    unsigned int u = __float_as_uint(x);
-    u += 0x7FFFu + ((u >> 16) & 1u);
-    return (unsigned short)(u >> 16);
-}
-
-__device__ __forceinline__ float bf16_to_f32(unsigned short b) { return __uint_as_float((unsigned int)b << 16); }
-
-// hi/lo pair of 8 values packed as two 16-byte vectors of bf16 bit patterns
+// hi/lo pair of 8 values packed as two 16-byte vectors of bf16 bit patterns, with the
+// hardware pair conversion (round to nearest even): hi = bf16(x), lo = bf16(x - hi)
 __device__ __forceinline__ void split8(const float* x, uint4& hi, uint4& lo) {
+    typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
     unsigned int h[4], l[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-        const unsigned short h0 = bf16_rne_bits(x[2 * q]), h1 = bf16_rne_bits(x[2 * q + 1]);
-        const unsigned short l0 = bf16_rne_bits(x[2 * q] - bf16_to_f32(h0));
-        const unsigned short l1 = bf16_rne_bits(x[2 * q + 1] - bf16_to_f32(h1));
-        h[q] = (unsigned int)h0 | ((unsigned int)h1 << 16);
-        l[q] = (unsigned int)l0 | ((unsigned int)l1 << 16);
+        const bf16x2 hv = {(__bf16)x[2 * q], (__bf16)x[2 * q + 1]};
+        h[q] = __builtin_bit_cast(unsigned int, hv);
+        const bf16x2 lv = {(__bf16)(x[2 * q] - __uint_as_float(h[q] << 16)),
+                           (__bf16)(x[2 * q + 1] - __uint_as_float(h[q] & 0xffff0000u))};
+        l[q] = __builtin_bit_cast(unsigned int, lv);
     }
     hi = make_uint4(h[0], h[1], h[2], h[3]);
     lo = make_uint4(l[0], l[1], l[2], l[3]);

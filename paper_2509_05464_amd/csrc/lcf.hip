@@ -264,18 +264,55 @@ __device__ __forceinline__ void gelu_tile(const floatx16& acc, uint16_t* actv, i
     }
 }
 
+// Layers 1-3 are streamed over 32-frame tiles: step s computes layer 1 on tile s, layer 2
+// on tile s-1 and layer 3 on tile s-2, so each layer's output only needs a ring of three
+// tile slots.  A slot holds its tile's 32 rows between 4 halo rows on each side (the taps
+// reach 4 frames into the neighbouring tiles): a tile's first 4 rows are also written into
+// the after-halo of the previous tile's slot and its last 4 into the before-halo of the
+// next one, so a tile's products read one contiguous 40-row window.  The halos outside the
+// series (before tile 0, after the last tile) are cleared.
+constexpr int SLOT = 40;   // rows per ring slot
+constexpr int RING_ELEMS = 3 * SLOT * RS;
+
+__device__ __forceinline__ void ring_store(unsigned short* ring, int s, int j, int h, const uint2* hv) {
+    const int cur = s % 3, prev = (s + 2) % 3, next = (s + 1) % 3;
+    unsigned short* body = ring + (cur * SLOT + 4 + j) * RS + 4 * h;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) *reinterpret_cast<uint2*>(body + 8 * q) = hv[q];
+    if (j < 4) {
+        unsigned short* p = ring + (prev * SLOT + 36 + j) * RS + 4 * h;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) *reinterpret_cast<uint2*>(p + 8 * q) = hv[q];
+    } else if (j >= 28) {
+        unsigned short* p = ring + (next * SLOT + j - 28) * RS + 4 * h;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) *reinterpret_cast<uint2*>(p + 8 * q) = hv[q];
+    }
+}
+__device__ __forceinline__ void ring_clear(unsigned short* ring, int first_row, int l) {
+    for (int i = l; i < 4 * RS / 4; i += 64) reinterpret_cast<uint2*>(ring + first_row * RS)[i] = make_uint2(0u, 0u);
+}
+
 // One wave per series at a time (grid-stride), two waves per SIMD: one wave's GELU
 // epilogue overlaps the other's matrix products.  Every layer, biases and the output
 // layer included, runs on the matrix cores; the weights stay in registers as MFMA
 // fragments.  The next series' samples are fetched into registers (XR per lane, frames
 // l, l+64, ...) while the current one is processed.
+// Up to 256 frames (XR = 4) one image of the whole series serves layers 1 and 2 (about
+// 20 KB, eight workgroups per CU); longer series stream the layers over tile rings, whose
+// size does not grow with the series.
 template <int XR, bool ACT>
 __global__ void __launch_bounds__(64, 2) lcf_fwd_kernel(const FwdArgs a) {
+    constexpr bool STREAM = XR > 4;
     extern __shared__ float4 smem4[];
     const Geo g(a.T);
     const int l = threadIdx.x;
-    unsigned short* h0 = reinterpret_cast<unsigned short*>(smem4);   // [TP+8][2]
-    unsigned short* hb = h0 + (g.TP + 8) * 2;                        // [TP][RS], layers 1 and 2
+    // streamed: ring of layer-1 tiles, ring of layer-2 tiles, input image [TP+8][2]
+    // whole:    input image [TP+8][2], image [TP][RS] of layer 1, then layer 2 in place
+    unsigned short* ra = reinterpret_cast<unsigned short*>(smem4);
+    unsigned short* rb = ra + RING_ELEMS;
+    unsigned short* h0 = STREAM ? rb + RING_ELEMS : ra;
+    unsigned short* hb = h0 + (g.TP + 8) * 2;
 
     u16x8 f1[K1C], f2[K2C], f3[K2C], f4[2];
     frag_fwd1(a.wb, a.w, l, f1);
@@ -284,10 +321,11 @@ __global__ void __launch_bounds__(64, 2) lcf_fwd_kernel(const FwdArgs a) {
     frag_out(a.wb, l, f4);
     const u16x8 fb2 = frag_bias(a.w, OFF_B2, l), fb3 = frag_bias(a.w, OFF_B3, l);
     const float b40 = a.w[OFF_B4], b41 = a.w[OFF_B4 + 1];
-    for (int i = l; i < (g.TP + 8) * 2 + g.TP * RS; i += 64) h0[i] = 0;   // padding rows stay zero
+    for (int i = l; i < (g.TP + 8) * 2 + (STREAM ? 0 : g.TP * RS); i += 64) h0[i] = 0;   // padding rows stay zero
     __builtin_amdgcn_wave_barrier();
 
     const int h = l / 32, j = l % 32;
+    const int last = (g.TT - 1) % 3;   // slot of the last tile
     float2 xn[XR];
     auto fetch = [&](int64_t v) {
 #pragma unroll
@@ -317,45 +355,18 @@ __global__ void __launch_bounds__(64, 2) lcf_fwd_kernel(const FwdArgs a) {
                 if (ACT) *reinterpret_cast<unsigned int*>(actv + act_off(0, g.T) + 2 * t) = p;
             }
         }
-        __builtin_amdgcn_wave_barrier();
-        // layer 1 -> hb; layer 2 -> hb in place: the output of a 32-frame tile is stored
-        // only after the next tile's products have read their inputs (the taps reach 4
-        // frames into the neighbouring tiles), so one image serves both layers
-        for (int tt = 0; tt < g.TT; ++tt) {
-            const floatx16 acc = conv2(h0, 32 * tt, f1, l);
-            const int t = 32 * tt + j;
-            uint2 hv[4];
-            gelu_tile<ACT>(acc, t < g.T ? actv : nullptr, 1, t, g.T, h, hv);
-#pragma unroll
-            for (int q = 0; q < 4; ++q) *reinterpret_cast<uint2*>(hb + (t + PADT) * RS + 8 * q + 4 * h) = hv[q];
-        }
-        __builtin_amdgcn_wave_barrier();
-        uint2 pend[4];
-        for (int tt = 0; tt < g.TT; ++tt) {
-            const floatx16 acc = conv32b(hb, 32 * tt, f2, fb2, l);
-            if (tt > 0) {
-#pragma unroll
-                for (int q = 0; q < 4; ++q)
-                    *reinterpret_cast<uint2*>(hb + (32 * tt - 32 + j + PADT) * RS + 8 * q + 4 * h) = pend[q];
-            }
-            const int t = 32 * tt + j;
-            gelu_tile<ACT>(acc, t < g.T ? actv : nullptr, 2, t, g.T, h, pend);
-        }
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-            *reinterpret_cast<uint2*>(hb + (32 * g.TT - 32 + j + PADT) * RS + 8 * q + 4 * h) = pend[q];
-        __builtin_amdgcn_wave_barrier();
-        // layer 3 and the output layer: y = W4 h3 (rows 0 and 1 of a 32-row product whose
-        // B operand is h3 as this lane already holds it) + b4
         float pdacc = 0.0f;
-        for (int tt = 0; tt < g.TT; ++tt) {
-            const floatx16 acc = conv32b(hb, 32 * tt, f3, fb3, l);
-            const int t = 32 * tt + j;
+        // layer 3 and the output layer on tile u of the image img (rows of tile u start at
+        // row 0): y = W4 h3 (rows 0 and 1 of a 32-row product whose B operand is h3 as this
+        // lane holds it) + b4
+        auto layer3 = [&](const unsigned short* img, int u) {
+            const floatx16 acc = conv32b(img, 0, f3, fb3, l);
+            const int t = 32 * u + j;
             uint2 hv[4];
             gelu_tile<ACT>(acc, t < g.T ? actv : nullptr, 3, t, g.T, h, hv);
             floatx16 yo;
 #pragma unroll
-            for (int r = 0; r < 16; ++r) yo[r] = 0.0f;
+            for (int i = 0; i < 16; ++i) yo[i] = 0.0f;
             yo = mfma(f4[0], __builtin_bit_cast(u16x8, make_uint4(hv[0].x, hv[0].y, hv[1].x, hv[1].y)), yo);
             yo = mfma(f4[1], __builtin_bit_cast(u16x8, make_uint4(hv[2].x, hv[2].y, hv[3].x, hv[3].y)), yo);
             if (h == 0 && t < g.T) {   // rows 0 and 1 of column j
@@ -363,6 +374,63 @@ __global__ void __launch_bounds__(64, 2) lcf_fwd_kernel(const FwdArgs a) {
                 pdacc += y0 * y0 + y1 * y1;
                 if (a.y) a.y[(int64_t)t * a.N + v] = make_float2(r * y0, r * y1);
             }
+        };
+        if (STREAM) {
+            ring_clear(ra, 0, l);   // before tile 0
+            ring_clear(rb, 0, l);
+            __builtin_amdgcn_wave_barrier();
+            for (int s = 0; s < g.TT + 2; ++s) {
+                if (s < g.TT) {   // layer 1, tile s
+                    const floatx16 acc = conv2(h0, 32 * s, f1, l);
+                    const int t = 32 * s + j;
+                    uint2 hv[4];
+                    gelu_tile<ACT>(acc, t < g.T ? actv : nullptr, 1, t, g.T, h, hv);
+                    ring_store(ra, s, j, h, hv);
+                } else if (s == g.TT) {
+                    ring_clear(ra, last * SLOT + 36, l);   // after the last tile
+                }
+                if (s >= 1 && s <= g.TT) {   // layer 2, tile s - 1
+                    const int u = s - 1;
+                    const floatx16 acc = conv32b(ra + (u % 3) * SLOT * RS, 0, f2, fb2, l);
+                    const int t = 32 * u + j;
+                    uint2 hv[4];
+                    gelu_tile<ACT>(acc, t < g.T ? actv : nullptr, 2, t, g.T, h, hv);
+                    ring_store(rb, u, j, h, hv);
+                } else if (s == g.TT + 1) {
+                    ring_clear(rb, last * SLOT + 36, l);
+                }
+                if (s >= 2) layer3(rb + ((s - 2) % 3) * SLOT * RS, s - 2);
+            }
+        } else {
+            __builtin_amdgcn_wave_barrier();
+            // layer 1 -> hb; layer 2 -> hb in place: the output of a 32-frame tile is
+            // stored only after the next tile's products have read their inputs (the taps
+            // reach 4 frames into the neighbouring tiles)
+            for (int tt = 0; tt < g.TT; ++tt) {
+                const floatx16 acc = conv2(h0, 32 * tt, f1, l);
+                const int t = 32 * tt + j;
+                uint2 hv[4];
+                gelu_tile<ACT>(acc, t < g.T ? actv : nullptr, 1, t, g.T, h, hv);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) *reinterpret_cast<uint2*>(hb + (t + PADT) * RS + 8 * q + 4 * h) = hv[q];
+            }
+            __builtin_amdgcn_wave_barrier();
+            uint2 pend[4];
+            for (int tt = 0; tt < g.TT; ++tt) {
+                const floatx16 acc = conv32b(hb, 32 * tt, f2, fb2, l);
+                if (tt > 0) {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        *reinterpret_cast<uint2*>(hb + (32 * tt - 32 + j + PADT) * RS + 8 * q + 4 * h) = pend[q];
+                }
+                const int t = 32 * tt + j;
+                gelu_tile<ACT>(acc, t < g.T ? actv : nullptr, 2, t, g.T, h, pend);
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                *reinterpret_cast<uint2*>(hb + (32 * g.TT - 32 + j + PADT) * RS + 8 * q + 4 * h) = pend[q];
+            __builtin_amdgcn_wave_barrier();
+            for (int tt = 0; tt < g.TT; ++tt) layer3(hb + 32 * tt * RS, tt);
         }
         pdacc = wave_sum(pdacc);
         if (a.pd && l == 0) a.pd[v] = r * r * pdacc / (float)g.T;
@@ -719,9 +787,9 @@ __global__ void fb_select_kernel(const float* pl, const float* ps, int64_t n, co
 
 constexpr int FB_BLOCKS = 512;
 
-size_t fwd_lds(int T) {
+size_t fwd_lds(int T) {   // the launch below takes the streamed kernel above 256 frames
     const int TP = 32 * ((T + 31) / 32) + 8;
-    return (size_t)(TP + 8) * 2 * 2 + (size_t)TP * RS * 2;
+    return (T > 256 ? 2 * (size_t)RING_ELEMS * 2 : (size_t)TP * RS * 2) + (size_t)(TP + 8) * 2 * 2;
 }
 size_t bwd_lds(int T) {
     const int TP = 32 * ((T + 31) / 32) + 8;
