@@ -246,6 +246,9 @@ int casorati_gram_noalloc(const float* iq, int64_t n_vox, int32_t n_t, int32_t g
  *  cutoff == FQ_CUTOFF_SSM (-2): K = the tissue rank that spatial_similarity (below) reads
  *     from the leading M = min(n_t, 64) spatial modes (K <= M/2).
  *  S_f = S - (S V_K) V_K^H (explicit subtraction);  pd[v] = (1/N_t) sum_f |S_f[v][f]|^2.
+ *     With iq_filt NULL and K <= 16, pd is the same sum taken as the FP64 difference
+ *     ||s_v||^2 - ||s_v V_K||^2 (s_v the voxel's row of S; V_K has orthonormal columns),
+ *     from one read of S, clamped at 0.
  *  iq       complex64 [n_t][n_vox];  gram complex128 [n_t][n_t] from casorati_gram;
  *  iq_filt  complex64 [n_t][n_vox] or NULL;  pd float32 [n_vox] or NULL;
  *  sigma    float64 [n_t] singular values, descending (device);

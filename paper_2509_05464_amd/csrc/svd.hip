@@ -814,18 +814,63 @@ __global__ void rank_kernel(const RankArgs a) {
     }
 }
 
-// FP32 copy of V_K, zero beyond column K (the projection runs whole size classes).
-__global__ void vk_kernel(const double2* vecs, const int* k_used, float2* vk, int n) {
+// FP32 copy of V_K [n][KMAX] and FP64 copy of its first KN columns [n][KN], both zero
+// beyond column K (the projections run whole size classes).
+constexpr int KN = 16;
+__global__ void vk_kernel(const double2* vecs, const int* k_used, float2* vk, double2* vk64, int n) {
     const int K = *k_used;
     for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < n * KMAX; idx += gridDim.x * blockDim.x) {
         const int f = idx / KMAX, k = idx % KMAX;
-        float2 v = make_float2(0.f, 0.f);
-        if (k < K) {
-            const double2 d = vecs[(size_t)f * n + k];
-            v = make_float2((float)d.x, (float)d.y);
-        }
-        vk[idx] = v;
+        double2 d = make_double2(0.0, 0.0);
+        if (k < K) d = vecs[(size_t)f * n + k];
+        vk[idx] = make_float2((float)d.x, (float)d.y);
+        if (k < KN) vk64[f * KN + k] = d;
     }
+}
+
+// Power Doppler alone (no filtered IQ) for K <= 16: V_K has orthonormal columns, so the
+// filtered energy of a voxel's row s of S is ||s - s V_K V_K^H||^2 = ||s||^2 - ||s V_K||^2
+// (Pythagoras), formed in FP64 (the clutter energy it cancels is up to ~1e6 times the
+// result) from one read of S.
+// One voxel per thread; V_K rows are uniform across the wavefront (scalar loads).  The
+// difference is clamped at zero, the value it rounds around when K removes every mode.
+struct PdNormArgs {
+    const float2* iq;     // [nt][nv]
+    const double2* vk64;  // [nt][KN]
+    const int* k_used;
+    float* pd;            // [nv]
+    int64_t nv;
+    int nt;
+    int k_lo;             // this instantiation serves k_lo < K <= KM
+};
+
+template <int KM>
+__global__ void __launch_bounds__(256) pd_norm_kernel(const PdNormArgs a) {
+    const int K = *a.k_used;
+    if (K <= a.k_lo || K > KM) return;
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= a.nv) return;
+    double cr[KM], ci[KM], nx = 0.0;
+#pragma unroll
+    for (int k = 0; k < KM; ++k) cr[k] = ci[k] = 0.0;
+    const float2* sv = a.iq + v;
+#pragma unroll 2
+    for (int f = 0; f < a.nt; ++f) {
+        const float2 x = sv[(int64_t)f * a.nv];
+        const double xr = x.x, xi = x.y;
+        nx = fma(xr, xr, fma(xi, xi, nx));
+        const double2* w = a.vk64 + f * KN;
+#pragma unroll
+        for (int k = 0; k < KM; ++k) {
+            const double2 u = w[k];   // c_k = sum_f s_f V[f][k] (s V_K for the row s of S)
+            cr[k] = fma(u.x, xr, fma(-u.y, xi, cr[k]));
+            ci[k] = fma(u.x, xi, fma(u.y, xr, ci[k]));
+        }
+    }
+    double c2 = 0.0;
+#pragma unroll
+    for (int k = 0; k < KM; ++k) c2 = fma(cr[k], cr[k], fma(ci[k], ci[k], c2));
+    a.pd[v] = (float)(fmax(nx - c2, 0.0) / a.nt);
 }
 
 struct PdArgs {
@@ -995,7 +1040,7 @@ TriFn tri_fn(int n) {
 
 struct SvdWs {
     size_t off_A, off_vh, off_tau, off_d, off_e, off_ri, off_rc, off_rs, off_rn, off_perm, off_Zs;
-    size_t off_lam, off_vecs, off_vk, off_k, off_ev, off_sc, off_zt, total;
+    size_t off_lam, off_vecs, off_vk, off_vk64, off_k, off_ev, off_sc, off_zt, total;
     int cap;
 };
 
@@ -1023,6 +1068,7 @@ SvdWs svd_layout(int n) {
     w.off_lam = take(sizeof(double) * n);
     w.off_vecs = take(sizeof(double2) * nn);
     w.off_vk = take(sizeof(float2) * (size_t)n * KMAX);
+    w.off_vk64 = take(sizeof(double2) * (size_t)n * KN);
     w.off_k = take(sizeof(int));
     w.off_ev = take(sizeof(double) * n);
     w.off_sc = take(sizeof(double));
@@ -1173,7 +1219,7 @@ extern "C" int svd_clutter_filter(const float* iq, int64_t n_vox, int32_t n_t, c
     }
     hipLaunchKernelGGL(vk_kernel, dim3((n_t * KMAX + 255) / 256), dim3(256), 0, s,
                        reinterpret_cast<const double2*>(vecs), static_cast<const int*>(k_used),
-                       reinterpret_cast<float2*>(w + L.off_vk), n_t);
+                       reinterpret_cast<float2*>(w + L.off_vk), reinterpret_cast<double2*>(w + L.off_vk64), n_t);
     FQ_LAUNCH_CHECK();
     if (!iq_filt && !pd) return FQ_OK;
     PdArgs pa{};
@@ -1186,6 +1232,28 @@ extern "C" int svd_clutter_filter(const float* iq, int64_t n_vox, int32_t n_t, c
     pa.nt = n_t;
     pa.inv_nt = 1.0f / (float)n_t;
     const unsigned blocks = (unsigned)((n_vox + PV * PW - 1) / (PV * PW));
+    if (!iq_filt) {
+        // power Doppler alone: the FP64 norm difference up to K = 16, the explicit
+        // projection above; all but the class holding K return at once
+        PdNormArgs na{pa.iq, reinterpret_cast<const double2*>(w + L.off_vk64), k_used, pd, n_vox, n_t, -1};
+        const unsigned nb = (unsigned)((n_vox + 255) / 256);
+        const int bounds[6] = {-1, 4, 8, 16, 32, 64};
+        for (int c = 0; c < 5; ++c) {
+            if (cutoff >= 0 && !(cutoff > bounds[c] && cutoff <= bounds[c + 1])) continue;
+            if (c < 3) {
+                na.k_lo = bounds[c];
+                auto kern = c == 0 ? pd_norm_kernel<4> : (c == 1 ? pd_norm_kernel<8> : pd_norm_kernel<16>);
+                hipLaunchKernelGGL(kern, dim3(nb), dim3(256), 0, s, na);
+            } else {
+                pa.k_lo = bounds[c];
+                const bool vl = project_vl(n_t, bounds[c + 1]);
+                hipLaunchKernelGGL(pd_fn(bounds[c + 1], vl), dim3(blocks), dim3(64 * PW),
+                                   project_mfma_lds(n_t, bounds[c + 1], vl), s, pa);
+            }
+            FQ_LAUNCH_CHECK();
+        }
+        return FQ_OK;
+    }
     if (cutoff >= 0) {
         const int km = cutoff <= 16 ? 16 : (cutoff <= 32 ? 32 : 64);
         pa.k_lo = -1;

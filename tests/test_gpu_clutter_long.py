@@ -118,3 +118,33 @@ def test_das_many_transmits(gpu, n_angles, interp):
     err = rel_l2(iq, want)
     print('das rel L2', err)
     assert err < 1e-4
+
+
+@pytest.mark.parametrize('nt', [20, 200])
+@pytest.mark.parametrize('K', [1, 4, 5, 8, 9, 16])
+def test_pd_alone_matches_explicit_projection(gpu, nt, K):
+    """Power Doppler without the filtered IQ takes the FP64 norm difference
+    ||s||^2 - ||s V_K||^2 up to K = 16; with the filtered IQ requested it is summed from
+    the explicit residual.  Both against the FP64 oracle and against each other."""
+    import torch
+    print('pd alone n_t', nt, 'K', K, flush=True)
+    nv = 9001   # ragged against every launch shape
+    iq = random_casorati(nv, nt, seed=K * 7 + nt, rank=6, tissue_db=45)
+    Go = clutter.gram(iq)
+    lam_o, V_o = clutter.eig_desc(Go)
+    pd_o = clutter.power_doppler(clutter.filter_iq(iq, V_o, K))
+    ws = torch.empty(gpu.svd_workspace_size(nv, nt), dtype=torch.uint8, device='cuda')
+    outs = []
+    for explicit in (False, True):
+        sigma = torch.empty(nt, dtype=torch.float64, device='cuda')
+        k = torch.zeros(1, dtype=torch.int32, device='cuda')
+        st = torch.full((1,), -1, dtype=torch.int32, device='cuda')
+        pd = torch.empty(nv, dtype=torch.float32, device='cuda')
+        iqf = torch.empty((nt, nv), dtype=torch.complex64, device='cuda') if explicit else None
+        gpu.svd_clutter_filter(dev(iq), dev(Go), ws, sigma, k, K, iq_filt=iqf, pd=pd, status=st)
+        assert int(st.item()) == 0 and int(k.item()) == K
+        outs.append(pd.cpu().numpy())
+    e_alone, e_expl, e_pair = rel_l2(outs[0], pd_o), rel_l2(outs[1], pd_o), rel_l2(outs[0], outs[1])
+    print(f'pd rel L2: alone {e_alone:.2e} explicit {e_expl:.2e} alone vs explicit {e_pair:.2e}')
+    assert e_alone < 1e-3 and e_expl < 1e-3 and e_pair < 1e-3
+    assert (outs[0] >= 0).all()
