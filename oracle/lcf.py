@@ -17,9 +17,13 @@ Blood estimate S_b[v,f] = s_v (y0 + i y1); loss = mean over (n, channel, t) of
 Parameter vector layout (float32 [19170]):
     W1 [32][2][9] | b1 [32] | W2 [32][32][9] | b2 [32] | W3 [32][32][9] | b3 [32] | W4 [2][32] | b4 [2]
 
-`bf16=True` rounds at the points the GPU kernels round (RNE): weights, the
-network input and each stored activation h1..h3 and pre-activation z1..z3 are
-BF16; the output-layer gradient and every accumulation stay wide.
+`bf16=True` rounds at the points the GPU kernels round (RNE): weights and each
+stored activation h1..h3 and pre-activation z1..z3 are BF16; the network input
+(FP32 after normalisation) is kept as two BF16 terms, hi = bf16(x) and
+lo = bf16(x - hi), whose sum carries ~16 significant bits (one BF16 alone puts its
+rounding noise ~59 dB below the series power, which tissue dominates, i.e. at the
+level of the weakest blood); the output-layer gradient and every accumulation stay
+wide.
 """
 from __future__ import annotations
 
@@ -99,12 +103,22 @@ def _q(a, on):
     return bf16_round(a.astype(np.float32)).astype(np.float64) if on else a
 
 
+def _q2(a, on):
+    """hi + lo: two BF16 terms of the FP32 value (the remainder x - hi is exact in FP32)."""
+    if not on:
+        return a
+    x = a.astype(np.float32)
+    hi = bf16_round(x)
+    lo = bf16_round((x - hi).astype(np.float32))
+    return hi.astype(np.float64) + lo.astype(np.float64)
+
+
 def forward(w: np.ndarray, x: np.ndarray, bf16: bool = False):
     """x [N][2][T] -> (y [N][2][T], cache)."""
     p = unpack(w)
     if bf16:
         p = {k: (_q(v, True) if k.startswith('W') else v) for k, v in p.items()}
-    h0 = _q(x, bf16)
+    h0 = _q2(x, bf16)
     z1 = conv(h0, p['W1'], p['b1'])
     h1 = _q(gelu(z1), bf16)
     z2 = conv(h1, p['W2'], p['b2'])

@@ -84,9 +84,9 @@ struct Geo {
     __device__ Geo(int t) : T(t), TT((t + 31) / 32), TP(32 * ((t + 31) / 32) + 8) {}
 };
 
-// per-series activation record (u16): h0 [T][2] (padded to 8) | z1 h1 z2 h2 z3 h3 [T][32];
-// every slot starts on a 16-byte boundary
-__host__ __device__ inline int64_t h0_len(int T) { return ((int64_t)2 * T + 7) / 8 * 8; }
+// per-series activation record (u16): h0 [T][2] hi terms, [T][2] lo terms (padded to 8) |
+// z1 h1 z2 h2 z3 h3 [T][32]; every slot starts on a 16-byte boundary
+__host__ __device__ inline int64_t h0_len(int T) { return ((int64_t)4 * T + 7) / 8 * 8; }
 __host__ __device__ inline int64_t act_stride(int T) { return h0_len(T) + (int64_t)6 * T * CH; }
 __host__ __device__ inline int64_t act_off(int which, int T) {   // 0:h0 1:z1 2:h1 3:z2 4:h2 5:z3 6:h3
     return which == 0 ? 0 : h0_len(T) + (int64_t)(which - 1) * T * CH;
@@ -209,9 +209,13 @@ __device__ void frag_out(const uint16_t* wb, int l, u16x8* fr) {
 
 // the input layer's conv: 2-channel image, 4 bytes per row; a lane's 8 consecutive kk are
 // taps 8c + 4h .. 8c + 4h + 3 of both channels, 16 contiguous bytes (4-byte aligned)
-__device__ __forceinline__ floatx16 conv2(const unsigned short* img, int t0, const u16x8* fr, int l) {
+// The input is two BF16 terms per value (hi = bf16(x), lo = bf16(x - hi)): the same
+// weights multiply the hi image and the lo image.
+__device__ __forceinline__ floatx16 conv2(const unsigned short* img, const unsigned short* img_lo, int t0,
+                                         const u16x8* fr, int l) {
     const int j = l % 32, h = l / 32;
     const unsigned int* im = reinterpret_cast<const unsigned int*>(img);
+    const unsigned int* il = reinterpret_cast<const unsigned int*>(img_lo);
     floatx16 acc;
 #pragma unroll
     for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
@@ -219,8 +223,13 @@ __device__ __forceinline__ floatx16 conv2(const unsigned short* img, int t0, con
     for (int c = 0; c < K1C; ++c) {
         const int row = t0 + j + 8 * c + 4 * h;
         uint4 w = make_uint4(im[row], im[row + 1], im[row + 2], im[row + 3]);
-        if (c == 1 && h == 0) w.y = w.z = BF_ONE2;   // B = 1 against the bias terms
+        uint4 wl = make_uint4(il[row], il[row + 1], il[row + 2], il[row + 3]);
+        if (c == 1 && h == 0) {   // B = 1 against the bias terms, once
+            w.y = w.z = BF_ONE2;
+            wl.y = wl.z = 0u;
+        }
         acc = mfma(fr[c], __builtin_bit_cast(u16x8, w), acc);
+        acc = mfma(fr[c], __builtin_bit_cast(u16x8, wl), acc);
     }
     return acc;
 }
@@ -307,12 +316,13 @@ __global__ void __launch_bounds__(64, 2) lcf_fwd_kernel(const FwdArgs a) {
     extern __shared__ float4 smem4[];
     const Geo g(a.T);
     const int l = threadIdx.x;
-    // streamed: ring of layer-1 tiles, ring of layer-2 tiles, input image [TP+8][2]
-    // whole:    input image [TP+8][2], image [TP][RS] of layer 1, then layer 2 in place
+    // streamed: ring of layer-1 tiles, ring of layer-2 tiles, input images (hi, lo) [TP+8][2]
+    // whole:    input images (hi, lo) [TP+8][2], image [TP][RS] of layer 1, then layer 2 in place
     unsigned short* ra = reinterpret_cast<unsigned short*>(smem4);
     unsigned short* rb = ra + RING_ELEMS;
     unsigned short* h0 = STREAM ? rb + RING_ELEMS : ra;
-    unsigned short* hb = h0 + (g.TP + 8) * 2;
+    unsigned short* hl = h0 + (g.TP + 8) * 2;   // lo terms of the input, [TP+8][2]
+    unsigned short* hb = hl + (g.TP + 8) * 2;
 
     u16x8 f1[K1C], f2[K2C], f3[K2C], f4[2];
     frag_fwd1(a.wb, a.w, l, f1);
@@ -321,7 +331,7 @@ __global__ void __launch_bounds__(64, 2) lcf_fwd_kernel(const FwdArgs a) {
     frag_out(a.wb, l, f4);
     const u16x8 fb2 = frag_bias(a.w, OFF_B2, l), fb3 = frag_bias(a.w, OFF_B3, l);
     const float b40 = a.w[OFF_B4], b41 = a.w[OFF_B4 + 1];
-    for (int i = l; i < (g.TP + 8) * 2 + (STREAM ? 0 : g.TP * RS); i += 64) h0[i] = 0;   // padding rows stay zero
+    for (int i = l; i < (g.TP + 8) * 4 + (STREAM ? 0 : g.TP * RS); i += 64) h0[i] = 0;   // padding rows stay zero
     __builtin_amdgcn_wave_barrier();
 
     const int h = l / 32, j = l % 32;
@@ -350,9 +360,15 @@ __global__ void __launch_bounds__(64, 2) lcf_fwd_kernel(const FwdArgs a) {
         for (int q = 0; q < XR; ++q) {
             const int t = l + 64 * q;
             if (t < g.T) {
-                const unsigned int p = f2bf2(xc[q].x * ir, xc[q].y * ir);
+                const float xr = xc[q].x * ir, xi = xc[q].y * ir;
+                const unsigned int p = f2bf2(xr, xi);
+                const unsigned int pl = f2bf2(xr - __uint_as_float(p << 16), xi - __uint_as_float(p & 0xffff0000u));
                 *reinterpret_cast<unsigned int*>(h0 + (t + PADT) * 2) = p;
-                if (ACT) *reinterpret_cast<unsigned int*>(actv + act_off(0, g.T) + 2 * t) = p;
+                *reinterpret_cast<unsigned int*>(hl + (t + PADT) * 2) = pl;
+                if (ACT) {
+                    *reinterpret_cast<unsigned int*>(actv + act_off(0, g.T) + 2 * t) = p;
+                    *reinterpret_cast<unsigned int*>(actv + act_off(0, g.T) + 2 * g.T + 2 * t) = pl;
+                }
             }
         }
         float pdacc = 0.0f;
@@ -381,7 +397,7 @@ __global__ void __launch_bounds__(64, 2) lcf_fwd_kernel(const FwdArgs a) {
             __builtin_amdgcn_wave_barrier();
             for (int s = 0; s < g.TT + 2; ++s) {
                 if (s < g.TT) {   // layer 1, tile s
-                    const floatx16 acc = conv2(h0, 32 * s, f1, l);
+                    const floatx16 acc = conv2(h0, hl, 32 * s, f1, l);
                     const int t = 32 * s + j;
                     uint2 hv[4];
                     gelu_tile<ACT>(acc, t < g.T ? actv : nullptr, 1, t, g.T, h, hv);
@@ -407,7 +423,7 @@ __global__ void __launch_bounds__(64, 2) lcf_fwd_kernel(const FwdArgs a) {
             // stored only after the next tile's products have read their inputs (the taps
             // reach 4 frames into the neighbouring tiles)
             for (int tt = 0; tt < g.TT; ++tt) {
-                const floatx16 acc = conv2(h0, 32 * tt, f1, l);
+                const floatx16 acc = conv2(h0, hl, 32 * tt, f1, l);
                 const int t = 32 * tt + j;
                 uint2 hv[4];
                 gelu_tile<ACT>(acc, t < g.T ? actv : nullptr, 1, t, g.T, h, hv);
@@ -606,7 +622,8 @@ __global__ void __launch_bounds__(64) lcf_wgrad_kernel(const WgArgs a) {
     const int l = threadIdx.x, h = l / 32, n = l % 32;
     unsigned short* dz = reinterpret_cast<unsigned short*>(smem4);   // [T16][32]
     unsigned short* hp = dz + T16 * CH;                              // [TP][HC]
-    for (int i = l; i < T16 * CH + g.TP * HC; i += 64) dz[i] = 0;
+    unsigned short* hq = hp + g.TP * HC;                             // layer 1: lo terms [TP][2]
+    for (int i = l; i < T16 * CH + g.TP * HC * (LAYER == 1 ? 2 : 1); i += 64) dz[i] = 0;
     __builtin_amdgcn_wave_barrier();
     const int zslot = 2 * LAYER - 1;                          // dz_L sits in z_L's slot
     const int hslot = LAYER == 1 ? 0 : 2 * (LAYER - 1);       // h_{L-1}
@@ -628,6 +645,8 @@ __global__ void __launch_bounds__(64) lcf_wgrad_kernel(const WgArgs a) {
             if (LAYER == 1) {
                 hp[(t + PADT) * 2] = av[act_off(0, g.T) + 2 * t];
                 hp[(t + PADT) * 2 + 1] = av[act_off(0, g.T) + 2 * t + 1];
+                hq[(t + PADT) * 2] = av[act_off(0, g.T) + 2 * g.T + 2 * t];
+                hq[(t + PADT) * 2 + 1] = av[act_off(0, g.T) + 2 * g.T + 2 * t + 1];
             } else {
 #pragma unroll
                 for (int q = 0; q < 4; ++q)
@@ -646,10 +665,15 @@ __global__ void __launch_bounds__(64) lcf_wgrad_kernel(const WgArgs a) {
 #pragma unroll
             for (int k = 0; k < NTILE; ++k) {
                 u16x8 B;
-                if (LAYER == 1) {
+                if (LAYER == 1) {   // dz (hi + lo): the hi product here, the lo one below
                     const int kk = min(n / 2, KW - 1), ii = n % 2;
+                    u16x8 Bl;
 #pragma unroll
-                    for (int q = 0; q < 8; ++q) B[q] = n < 18 ? hp[(t0 + 8 * h + q + kk) * 2 + ii] : (unsigned short)0;
+                    for (int q = 0; q < 8; ++q) {
+                        B[q] = n < 18 ? hp[(t0 + 8 * h + q + kk) * 2 + ii] : (unsigned short)0;
+                        Bl[q] = n < 18 ? hq[(t0 + 8 * h + q + kk) * 2 + ii] : (unsigned short)0;
+                    }
+                    acc[k] = mfma(A, Bl, acc[k]);
                 } else {
 #pragma unroll
                     for (int q = 0; q < 8; ++q) B[q] = hp[(t0 + 8 * h + q + k) * CH + n];
@@ -789,7 +813,7 @@ constexpr int FB_BLOCKS = 512;
 
 size_t fwd_lds(int T) {   // the launch below takes the streamed kernel above 256 frames
     const int TP = 32 * ((T + 31) / 32) + 8;
-    return (T > 256 ? 2 * (size_t)RING_ELEMS * 2 : (size_t)TP * RS * 2) + (size_t)(TP + 8) * 2 * 2;
+    return (T > 256 ? 2 * (size_t)RING_ELEMS * 2 : (size_t)TP * RS * 2) + (size_t)(TP + 8) * 4 * 2;
 }
 size_t bwd_lds(int T) {
     const int TP = 32 * ((T + 31) / 32) + 8;
@@ -797,7 +821,7 @@ size_t bwd_lds(int T) {
 }
 size_t wg_lds(int T, int layer) {
     const int TP = 32 * ((T + 31) / 32) + 8, T16 = (T + 15) / 16 * 16;
-    return (size_t)T16 * CH * 2 + (size_t)TP * (layer == 1 ? 2 : CH) * 2;
+    return (size_t)T16 * CH * 2 + (size_t)TP * (layer == 1 ? 4 : CH) * 2;
 }
 size_t act_bytes(int64_t n, int T) { return round_up((size_t)n * act_stride(T) * 2, 256); }
 size_t part_bytes() { return (size_t)NWB * (PART1 + 2 * PART + PART4) * 4; }
