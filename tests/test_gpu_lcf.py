@@ -41,7 +41,7 @@ def _gpu_forward(gpu, w, wb, x_tn, act=None):
     return y.cpu().numpy(), pd.cpu().numpy()
 
 
-@pytest.mark.parametrize('T,n', [(24, 37), (200, 64), (65, 5), (257, 9), (512, 7), (12, 8200)])
+@pytest.mark.parametrize('T,n', [(24, 37), (200, 64), (65, 5), (40, 11), (32, 3), (100, 6), (257, 9), (512, 7), (12, 8200)])
 def test_forward_matches_oracle(gpu, T, n):
     w, wb = _weights(1)
     mix, _ = _series(2, n, T)
