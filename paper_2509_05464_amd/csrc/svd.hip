@@ -208,6 +208,237 @@ __global__ void __launch_bounds__(TRI_THREADS) tridiag_kernel(const TriArgs a) {
     }
 }
 
+// Register-resident form for n <= RT_N: the lower triangle of A (the Hermitian matrix) is
+// held in the registers of one workgroup for the whole reduction, so a step reads and
+// writes no global memory.  The triangle is cut into 16x16 blocks (I >= J), listed by
+// block column J descending and I ascending and dealt to the 16 wavefronts in turn (a
+// wavefront keeps blocks across the whole matrix, so the shrinking trailing block stays
+// spread over all of them); in a block, lane l holds rows 4(l/16) .. 4(l/16)+3 of column
+// l%16.  Step k:
+//   1. the owners of column k put A[k..n-1][k] in LDS;
+//   2. one wavefront forms the reflector (same formulas as the kernel above);
+//   3. p = A22 v: each stored A_ij (i > j) adds A_ij v_j to p_i and conj(A_ij) v_i to p_j
+//      (the diagonal only the first): row sums are reduced over the block's 16 columns by
+//      a halving butterfly (each exchange halves the values a lane carries), column sums
+//      over its 4 row groups, both added into p with LDS atomics;
+//   4. every wavefront forms r = v^H p itself, and w = tau p - |tau|^2 r v / 2 on the fly;
+//   5. A22 -= v w^H + w v^H on the stored elements with j > k.
+// v and p alternate between two buffers by step parity, so a step's writes never meet
+// the previous step's reads (three barriers per step).
+constexpr int RT_N = 208;                  // 13 block rows: 91 blocks, at most 6 per wavefront
+constexpr int RT_BPW = 6;                  // blocks per wavefront
+constexpr int RT_REG = 4;                  // of them in registers; the rest in LDS (lane-private)
+
+__device__ __forceinline__ void rt_block(int b, int nbr, int& I, int& J) {
+    I = J = -1;
+    for (int jj = nbr - 1; jj >= 0; --jj) {
+        const int cnt = nbr - jj;
+        if (b < cnt) {
+            J = jj;
+            I = jj + b;
+            return;
+        }
+        b -= cnt;
+    }
+}
+
+// step 3 on one block (rows i0 .. i0+3 of column j in this lane)
+__device__ __forceinline__ void rt_matvec(const double2 (&x)[4], int i0, int j, int n, int c, int lane,
+                                          const double2* v, double2* p) {
+    const double2 vj = v[j];
+    double d[8];
+    double2 cs = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const double2 r = zmul(x[q], vj);
+        d[2 * q] = r.x;
+        d[2 * q + 1] = r.y;
+        if (i0 + q > j) {
+            const double2 t = zmul(zconj(x[q]), v[i0 + q]);
+            cs.x += t.x;
+            cs.y += t.y;
+        }
+    }
+    // row sums over the 16 lanes of this row group: halving butterfly on c
+    const bool b3 = c & 8, b2 = c & 4, b1 = c & 2;
+    double e4[4], e2[2];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) e4[m] = (b3 ? d[4 + m] : d[m]) + __shfl_xor(b3 ? d[m] : d[4 + m], 8);
+#pragma unroll
+    for (int m = 0; m < 2; ++m) e2[m] = (b2 ? e4[2 + m] : e4[m]) + __shfl_xor(b2 ? e4[m] : e4[2 + m], 4);
+    double e1 = (b1 ? e2[1] : e2[0]) + __shfl_xor(b1 ? e2[0] : e2[1], 2);
+    e1 += __shfl_xor(e1, 1);
+    if ((c & 1) == 0) {   // value 4 b3 + 2 b2 + b1: row q = 2 b3 + b2, part b1
+        const int idx = (b3 ? 4 : 0) + (b2 ? 2 : 0) + (b1 ? 1 : 0);
+        atomicAdd(reinterpret_cast<double*>(p + i0 + (idx >> 1)) + (idx & 1), e1);
+    }
+    // column sums over the block's 4 row groups
+    cs.x += __shfl_xor(cs.x, 16);
+    cs.y += __shfl_xor(cs.y, 16);
+    cs.x += __shfl_xor(cs.x, 32);
+    cs.y += __shfl_xor(cs.y, 32);
+    if (lane < 16 && j < n) {
+        atomicAdd(&p[j].x, cs.x);
+        atomicAdd(&p[j].y, cs.y);
+    }
+}
+
+// step 5 on one block: A -= v w^H + w v^H, w = tau p - hw v, for this lane's stored elements
+__device__ __forceinline__ void rt_update(double2 (&x)[4], int i0, int j, int n, const double2* v, const double2* p,
+                                          double2 tau, double hw) {
+    const double2 vj = v[j], tpj = zmul(tau, p[j]);
+    const double2 wj = make_double2(tpj.x - hw * vj.x, tpj.y - hw * vj.y);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int i = i0 + q;
+        if (i >= j && i < n) {
+            const double2 vi = v[i], tpi = zmul(tau, p[i]);
+            const double2 wi = make_double2(tpi.x - hw * vi.x, tpi.y - hw * vi.y);
+            const double2 u1 = zmulc(vi, wj), u2 = zmulc(wi, vj);
+            x[q].x -= u1.x + u2.x;
+            x[q].y -= u1.y + u2.y;
+        }
+    }
+}
+
+__global__ void __launch_bounds__(TRI_THREADS) tridiag_reg_kernel(const TriArgs a) {
+    __shared__ double2 col[RT_N];
+    __shared__ double2 sv[2][RT_N], sp[2][RT_N];
+    __shared__ double2 s_tau;
+    // blocks RT_REG .. RT_BPW-1 of each wavefront: [wave][block][q][lane]
+    __shared__ double2 AL[(TRI_THREADS / 64) * (RT_BPW - RT_REG) * 4 * 64];
+    const int n = a.n, tid = threadIdx.x, lane = tid & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);   // uniform: block bookkeeping in scalars
+    const int nbr = (n + 15) / 16;
+    const int c = lane & 15, rb = (lane >> 4) * 4;
+    for (int i = tid; i < RT_N; i += TRI_THREADS) {
+        col[i] = sv[0][i] = sv[1][i] = sp[0][i] = sp[1][i] = make_double2(0.0, 0.0);
+    }
+    auto lds_blk = [&](int s, int q) -> double2& { return AL[((wv * (RT_BPW - RT_REG) + s - RT_REG) * 4 + q) * 64 + lane]; };
+    int bI[RT_BPW], bJ[RT_BPW];
+    double2 A[RT_REG][4];
+#pragma unroll
+    for (int s = 0; s < RT_BPW; ++s) {
+        rt_block(wv + 16 * s, nbr, bI[s], bJ[s]);
+        const int j = 16 * bJ[s] + c;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int i = 16 * bI[s] + rb + q;
+            double2 x = make_double2(0.0, 0.0);
+            if (bI[s] >= 0 && i < n && j < n && i >= j) {
+                // Hermitian part of the input (the Gram is Hermitian up to its own rounding)
+                const double2 g = a.G[(size_t)i * n + j], gt = a.G[(size_t)j * n + i];
+                x = i == j ? make_double2(g.x, 0.0) : make_double2(0.5 * (g.x + gt.x), 0.5 * (g.y - gt.y));
+            }
+            if (s < RT_REG) A[s][q] = x;
+            else lds_blk(s, q) = x;
+        }
+    }
+    __syncthreads();
+    for (int k = 0; k < n - 1; ++k) {
+        double2* v = sv[k & 1];
+        double2* p = sp[k & 1];
+        // 1. column k, rows k .. n-1; clear p
+        const int kb = k >> 4, kc = k & 15;
+#pragma unroll
+        for (int s = 0; s < RT_BPW; ++s) {
+            if (bJ[s] == kb && c == kc) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int i = 16 * bI[s] + rb + q;
+                    if (i >= k && i < n) col[i] = s < RT_REG ? A[s < RT_REG ? s : 0][q] : lds_blk(s, q);
+                }
+            }
+        }
+        for (int i = tid; i < n; i += TRI_THREADS) p[i] = make_double2(0.0, 0.0);
+        __syncthreads();
+        // 2. the reflector of column k
+        if (wv == 0) {
+            double ps = 0.0;
+            for (int i = k + 2 + lane; i < n; i += 64) ps += col[i].x * col[i].x + col[i].y * col[i].y;
+            for (int o = 32; o > 0; o >>= 1) ps += __shfl_xor(ps, o);
+            const double sigma = ps;
+            const double2 alpha = col[k + 1];
+            double2 tau = make_double2(0.0, 0.0), scale = make_double2(0.0, 0.0);
+            double beta = alpha.x;
+            if (sigma > 0.0 || alpha.y != 0.0) {
+                const double nrm = sqrt(alpha.x * alpha.x + alpha.y * alpha.y + sigma);
+                beta = alpha.x >= 0.0 ? -nrm : nrm;
+                tau = make_double2((beta - alpha.x) / beta, -alpha.y / beta);
+                const double2 den = make_double2(alpha.x - beta, alpha.y);   // 1 / (alpha - beta)
+                const double dd = den.x * den.x + den.y * den.y;
+                scale = make_double2(den.x / dd, -den.y / dd);
+            }
+            if (lane == 0) {
+                a.tau[k] = tau;
+                a.e[k] = beta;
+                a.d[k] = col[k].x;
+                s_tau = tau;
+            }
+            for (int i = lane; i < n; i += 64) {
+                double2 vi = make_double2(0.0, 0.0);
+                if (i == k + 1) vi = make_double2(1.0, 0.0);
+                else if (i > k + 1) vi = zmul(col[i], scale);
+                v[i] = vi;
+                if (i > k) a.vh[(size_t)k * n + i] = vi;
+            }
+        }
+        __syncthreads();
+        const double2 tau = s_tau;
+        // 3. p = A22 v (blocks with a column beyond k)
+#pragma unroll
+        for (int s = 0; s < RT_BPW; ++s) {
+            if (bI[s] < 0 || 16 * bJ[s] + 15 <= k) continue;
+            const int j = 16 * bJ[s] + c, i0 = 16 * bI[s] + rb;
+            if (s < RT_REG) {
+                rt_matvec(A[s < RT_REG ? s : 0], i0, j, n, c, lane, v, p);
+            } else {
+                double2 x[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) x[q] = lds_blk(s, q);
+                rt_matvec(x, i0, j, n, c, lane, v, p);
+            }
+        }
+        __syncthreads();
+        // 4. r = v^H p (real), in every wavefront
+        double pr = 0.0;
+        for (int i = k + 1 + lane; i < n; i += 64) pr += v[i].x * p[i].x + v[i].y * p[i].y;
+        for (int o = 32; o > 0; o >>= 1) pr += __shfl_xor(pr, o);
+        const double hw = 0.5 * (tau.x * tau.x + tau.y * tau.y) * pr;
+        // 5. the rank-2 update on columns beyond k
+#pragma unroll
+        for (int s = 0; s < RT_BPW; ++s) {
+            if (bI[s] < 0 || 16 * bJ[s] + 15 <= k) continue;
+            const int j = 16 * bJ[s] + c, i0 = 16 * bI[s] + rb;
+            if (j <= k || j >= n) continue;
+            if (s < RT_REG) {
+                rt_update(A[s < RT_REG ? s : 0], i0, j, n, v, p, tau, hw);
+            } else {
+                double2 x[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) x[q] = lds_blk(s, q);
+                rt_update(x, i0, j, n, v, p, tau, hw);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) lds_blk(s, q) = x[q];
+            }
+        }
+    }
+    // the last diagonal element
+    const int m = n - 1;
+#pragma unroll
+    for (int s = 0; s < RT_BPW; ++s) {
+        if (bJ[s] == (m >> 4) && bI[s] == (m >> 4) && c == (m & 15)) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                if (16 * bI[s] + rb + q == m) {
+                    a.d[m] = s < RT_REG ? A[s < RT_REG ? s : 0][q].x : lds_blk(s, q).x;
+                    a.e[m] = 0.0;
+                }
+            }
+        }
+    }
+}
+
 // ------------------------------------------------------------------ 2. QL on T
 struct QlArgs {
     const double* d;
@@ -1034,6 +1265,7 @@ __global__ void __launch_bounds__(256) pd_kernel(const float2* iq, int64_t nv, i
 
 using TriFn = void (*)(const TriArgs);
 TriFn tri_fn(int n) {
+    if (n <= RT_N) return tridiag_reg_kernel;
     if (n <= 256) return tridiag_kernel<4>;
     return tridiag_kernel<FQ_MAX_NT / 64>;
 }

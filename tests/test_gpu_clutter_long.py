@@ -1,6 +1,7 @@
 """Clutter filter at long ensembles (the large configuration's 400 frames and the ABI
-limit of 512), and the beamformer with more transmits than one pass over its staged
-delay windows holds, against the FP64 oracle.
+limit of 512; the eigensolver also on both sides of the register-resident reduction's
+limit of 208 frames and with partial last block rows), and the beamformer with more
+transmits than one pass over its staged delay windows holds, against the FP64 oracle.
 
 Ensembles: a seeded Casorati matrix with a rank-6 tissue part (amplitudes 6 dB apart), white
 blood 45 dB below it and a noise floor.  The FP64 oracle's Gram is handed to the GPU
@@ -22,7 +23,7 @@ def _casorati(nt, seed):
     return random_casorati(NV, nt, seed=seed, rank=6, tissue_db=45)
 
 
-@pytest.mark.parametrize('nt', [400, 512])
+@pytest.mark.parametrize('nt', [17, 100, 193, 200, 208, 209, 400, 512])
 def test_eig_long_ensemble(gpu, nt):
     import torch
     print('eig n_t', nt, flush=True)
