@@ -220,6 +220,63 @@ def das_only(cfg, args, fq, torch, dev):
                       'tflops': DAS_FLOP_PER_UNIT * units / (ms / 1e3) / 1e12}))
 
 
+def filters_only(cfg, args, fq, torch, dev):
+    """The three power-Doppler paths (FP32 SVD, four-product split-BF16 SVD, learned inference)
+    on the workload's own ensemble (scene -> RF -> DAS, untimed), each run `steps` times after
+    `warmup`, for profiler runs (kernel traces and counters of the Gram, eigensolver,
+    projection and learned-filter kernels)."""
+    from paper_2509_05464_amd.learned import LearnedFilter
+    from fqscene import lcf_init_weights, make_scene
+    acq = cfg.acq
+    F, A, E, T, NV = acq.n_frames, acq.n_angles, acq.n_elem, acq.n_samples, acq.n_vox
+    sc = make_scene(cfg)
+    probe = fq.make_probe(acq.nx_el, acq.ny_el, acq.pitch, acq.pitch, acq.fc, acq.fs, acq.c)
+    tx = fq.make_tx(acq.tilts_rad())
+    grid = fq.make_grid(acq.nx, acq.ny, acq.nz, acq.x0, acq.y0, acq.z0, acq.dx, acq.dy, acq.dz)
+    pulse = fq.make_pulse(2.0, 5.0, 1e-3)
+    rf = torch.empty((F, A, E, T), dtype=torch.float32, device=dev)
+    t_pos, t_amp = torch.from_numpy(sc.tissue_pos).to(dev), torch.from_numpy(sc.tissue_amp).to(dev)
+    b_pos, b_amp = torch.from_numpy(sc.blood_pos).to(dev), torch.from_numpy(sc.blood_amp).to(dev)
+    fq.rf_synth(probe, tx, pulse, t_pos, t_amp, rf, pos_static=sc.tissue_static, accumulate=False)
+    fq.rf_synth(probe, tx, pulse, b_pos, b_amp, rf, pos_static=False, accumulate=True)
+    das_ws = torch.empty(fq.das_workspace_size(probe, tx, F, T), dtype=torch.uint8, device=dev)
+    iq = torch.empty((F, NV), dtype=torch.complex64, device=dev)
+    fq.das_demodulate(probe, tx, rf, das_ws)
+    fq.das_delay_sum(probe, tx, grid, T, das_ws, iq, fq.INTERP_LINEAR)
+    del rf, das_ws
+    torch.cuda.empty_cache()
+    wpath = os.path.join(ROOT, 'paper_2509_05464_amd', 'weights', 'lcf_c4.npz')
+    filt = LearnedFilter.load(wpath, dev) if os.path.exists(wpath) else LearnedFilter(lcf_init_weights(0), dev)
+    gws = torch.empty(fq.gram_workspace_size(NV, F, 0), dtype=torch.uint8, device=dev)
+    sws = torch.empty(fq.svd_workspace_size(NV, F), dtype=torch.uint8, device=dev)
+    G = torch.empty((F, F), dtype=torch.complex128, device=dev)
+    sig = torch.empty(F, dtype=torch.float64, device=dev)
+    k = torch.zeros(1, dtype=torch.int32, device=dev)
+    st = torch.zeros(1, dtype=torch.int32, device=dev)
+    pd = torch.empty(NV, dtype=torch.float32, device=dev)
+    paths = {
+        'svd_fp32': lambda: (fq.casorati_gram(iq, G, gws, fq.GRAM_FP32),
+                             fq.svd_clutter_filter(iq, G, sws, sig, k, cfg.cutoff, pd=pd, status=st)),
+        'svd_split4_bf16': lambda: (fq.casorati_gram(iq, G, gws, fq.GRAM_SPLIT4_BF16),
+                                    fq.svd_clutter_filter(iq, G, sws, sig, k, cfg.cutoff, pd=pd, status=st)),
+        'learned': lambda: filt.infer(iq, pd),
+    }
+    out = {'workload': cfg.name, 'ms_per_volume': {}}
+    for name, fn in paths.items():
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(args.steps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        out['ms_per_volume'][name] = e0.elapsed_time(e1) / max(1, args.steps)
+    out['k_used'] = int(k.item())
+    print(json.dumps(out))
+
+
 def rf_only(cfg, args, fq, torch, dev):
     """RF synthesis of the workload's scene (tissue, then blood added), for profiler runs."""
     from fqscene import make_scene
@@ -783,11 +840,12 @@ def main():
     ap.add_argument('--serial', action='store_true', help='run the filters after the beamformer on one stream')
     ap.add_argument('--no-truth', action='store_true', help='skip the untimed ground-truth error pass')
     ap.add_argument('--fd-frames', type=int, default=None, help='frames of the frequency-domain run (--only fd)')
-    ap.add_argument('--only', choices=['das', 'rf', 'fd', 'roof'], default=None,
+    ap.add_argument('--only', choices=['das', 'rf', 'fd', 'roof', 'filters'], default=None,
                     help='das: the delay-and-sum kernel alone on the workload geometry (seeded random RF), '
                          'plus a 2 GiB device copy that calibrates byte counters; rf: RF synthesis of the '
                          'workload scene alone; fd: frequency-domain RF synthesis of the workload scene; '
-                         'roof: the LDS-bandwidth and FP32-FMA probes; for profiler runs')
+                         'roof: the LDS-bandwidth and FP32-FMA probes; filters: the three power-Doppler '
+                         'paths on a seeded random ensemble of the workload shape; for profiler runs')
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({'error': 'the path runs on one GPU: --gpus must be 1 (sharding across GPUs is designed, '
@@ -809,6 +867,8 @@ def main():
         return fd_only(cfg, args, fq, torch, dev)
     if args.only == 'roof':
         return roof_only(fq, torch, dev)
+    if args.only == 'filters':
+        return filters_only(cfg, args, fq, torch, dev)
 
     # learned filter: trained weights when present, and a small training set (untimed)
     from paper_2509_05464_amd.learned import LearnedFilter

@@ -242,6 +242,19 @@ __device__ __forceinline__ void rt_block(int b, int nbr, int& I, int& J) {
     }
 }
 
+// Lane exchanges inside a row of 16 lanes on the VALU (DPP), for FP64 values:
+// row_ror:n gives lane x the value of lane (x - n) mod 16 of its row; quad_perm swaps.
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double x) {
+    const long long u = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)u, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(u >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+constexpr int DPP_XOR1 = 0xB1;       // quad_perm [1, 0, 3, 2]
+constexpr int DPP_XOR2 = 0x4E;       // quad_perm [2, 3, 0, 1]
+constexpr int DPP_ROR4 = 0x124, DPP_ROR8 = 0x128, DPP_ROR12 = 0x12C;
+
 // step 3 on one block (rows i0 .. i0+3 of column j in this lane)
 __device__ __forceinline__ void rt_matvec(const double2 (&x)[4], int i0, int j, int n, int c, int lane,
                                           const double2* v, double2* p) {
@@ -259,15 +272,21 @@ __device__ __forceinline__ void rt_matvec(const double2 (&x)[4], int i0, int j, 
             cs.y += t.y;
         }
     }
-    // row sums over the 16 lanes of this row group: halving butterfly on c
+    // row sums over the 16 lanes of this row group: halving butterfly on c, partners c ^ 8,
+    // c ^ 4, c ^ 2, c ^ 1 (the row's lanes, exchanged by DPP: c ^ 8 is a rotation by 8, c ^ 4
+    // a rotation by 4 for the lanes with bit 2 set and by 12 for the others)
     const bool b3 = c & 8, b2 = c & 4, b1 = c & 2;
     double e4[4], e2[2];
 #pragma unroll
-    for (int m = 0; m < 4; ++m) e4[m] = (b3 ? d[4 + m] : d[m]) + __shfl_xor(b3 ? d[m] : d[4 + m], 8);
+    for (int m = 0; m < 4; ++m) e4[m] = (b3 ? d[4 + m] : d[m]) + dpp_f64<DPP_ROR8>(b3 ? d[m] : d[4 + m]);
 #pragma unroll
-    for (int m = 0; m < 2; ++m) e2[m] = (b2 ? e4[2 + m] : e4[m]) + __shfl_xor(b2 ? e4[m] : e4[2 + m], 4);
-    double e1 = (b1 ? e2[1] : e2[0]) + __shfl_xor(b1 ? e2[0] : e2[1], 2);
-    e1 += __shfl_xor(e1, 1);
+    for (int m = 0; m < 2; ++m) {
+        const double snd = b2 ? e4[m] : e4[2 + m];
+        const double a4 = dpp_f64<DPP_ROR4>(snd), a12 = dpp_f64<DPP_ROR12>(snd);
+        e2[m] = (b2 ? e4[2 + m] : e4[m]) + (b2 ? a4 : a12);
+    }
+    double e1 = (b1 ? e2[1] : e2[0]) + dpp_f64<DPP_XOR2>(b1 ? e2[0] : e2[1]);
+    e1 += dpp_f64<DPP_XOR1>(e1);
     if ((c & 1) == 0) {   // value 4 b3 + 2 b2 + b1: row q = 2 b3 + b2, part b1
         const int idx = (b3 ? 4 : 0) + (b2 ? 2 : 0) + (b1 ? 1 : 0);
         atomicAdd(reinterpret_cast<double*>(p + i0 + (idx >> 1)) + (idx & 1), e1);
@@ -356,7 +375,12 @@ __global__ void __launch_bounds__(TRI_THREADS) tridiag_reg_kernel(const TriArgs 
         if (wv == 0) {
             double ps = 0.0;
             for (int i = k + 2 + lane; i < n; i += 64) ps += col[i].x * col[i].x + col[i].y * col[i].y;
-            for (int o = 32; o > 0; o >>= 1) ps += __shfl_xor(ps, o);
+            ps += dpp_f64<DPP_XOR1>(ps);
+            ps += dpp_f64<DPP_XOR2>(ps);
+            ps += dpp_f64<DPP_ROR4>(ps);   // then lanes x and x - 4 of the row summed
+            ps += dpp_f64<DPP_ROR8>(ps);   // and x - 8, x - 12: the row's total
+            ps += __shfl_xor(ps, 16);
+            ps += __shfl_xor(ps, 32);
             const double sigma = ps;
             const double2 alpha = col[k + 1];
             double2 tau = make_double2(0.0, 0.0), scale = make_double2(0.0, 0.0);
