@@ -23,7 +23,10 @@
 // order (deterministic).
 // Workgroups that share a voxel range are placed on the same XCD so the range is read
 // from HBM once and served to the other groups from that XCD's L2.
+#include <algorithm>
+#include <cstring>
 #include <mutex>
+#include <vector>
 
 #include "fq_common.hpp"
 
@@ -34,13 +37,20 @@ typedef float floatx16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 constexpr int GT = 32;            // tile edge, frames
-constexpr int GG = 2;             // tiles per group edge
-constexpr int GR = GG * GT;       // frames per group edge
+constexpr int GR = 2 * GT;        // LDS stage: 4 frame blocks (2 GR rows)
+constexpr int GMAX = 34;          // tile groups at n_t = 512 (136 tiles, 4 per group)
 constexpr int KC = 64;            // voxels per LDS stage
 constexpr int LDW = KC + 4;       // FP32 LDS row stride (floats)
 constexpr int LDB = KC + 8;       // BF16 LDS row stride (bf16 values; 144-byte rows)
 constexpr int GRAM_THREADS = 256;
 constexpr int NXCD = 8;
+
+// A workgroup's four tiles (one per wavefront; 255 = none) and the at most four frame
+// blocks they read (255 = none): the blocks fill the LDS stage's four 32-row slots.
+struct GroupTab {
+    unsigned char ij[GMAX][4][2];
+    unsigned char blk[GMAX][4];
+};
 
 struct GramArgs {
     const float2* iq;     // [nt][nv]
@@ -48,18 +58,9 @@ struct GramArgs {
     int64_t nv;
     int64_t chunk;        // voxels per split
     int nt, nb, ntiles, nsplit;
-    int nbg, ngroups;     // tile groups per edge, groups in the upper triangle
+    int ngroups;          // tile groups
+    GroupTab tab;
 };
-
-__device__ __forceinline__ void tile_ij(int t, int nb, int& I, int& J) {
-    int i = 0;
-    while (t >= nb - i) {
-        t -= nb - i;
-        ++i;
-    }
-    I = i;
-    J = i + t;
-}
 
 // hi/lo pair of 8 values packed as two 16-byte vectors of bf16 bit patterns, with the
 // hardware pair conversion (round to nearest even): hi = bf16(x), lo = bf16(x - hi)
@@ -97,18 +98,18 @@ __global__ void __launch_bounds__(GRAM_THREADS, 2) gram_kernel(const GramArgs a)
     const int grp = loc % a.ngroups;
     const int split = (loc / a.ngroups) * NXCD + xcd;
     if (split >= a.nsplit) return;
-    int gi, gj;
-    tile_ij(grp, a.nbg, gi, gj);
-    const bool diag = gi == gj;
     const int64_t v_begin = (int64_t)split * a.chunk;
     const int64_t v_end = min(a.nv, v_begin + a.chunk);
 
     const int w = threadIdx.x / 64, l = threadIdx.x % 64;
-    const int pi = w / GG, qj = w % GG;
-    const int I = gi * GG + pi, J = gj * GG + qj;
-    const bool active = I <= J && J < a.nb;      // the group's lower tile on the diagonal is skipped
-    const int xrow = pi * GT;                    // stage rows of block I
-    const int yrow = (diag ? 0 : GR) + qj * GT;  // stage rows of block J (shared with I on the diagonal)
+    const int I = a.tab.ij[grp][w][0], J = a.tab.ij[grp][w][1];
+    const bool active = I != 255;
+    int xrow = 0, yrow = 0;   // stage rows of blocks I and J
+#pragma unroll
+    for (int sl = 0; sl < 4; ++sl) {
+        if (a.tab.blk[grp][sl] == I) xrow = sl * GT;
+        if (a.tab.blk[grp][sl] == J) yrow = sl * GT;
+    }
 
     // Re G = Re.Re + Im.Im and Im G = Re.Im - Im.Re accumulate directly (the second term of
     // Im G through a negated operand): FP32 within a stage, FP64 across stages
@@ -123,8 +124,9 @@ __global__ void __launch_bounds__(GRAM_THREADS, 2) gram_kernel(const GramArgs a)
     // loader mapping: up to 128 rows x 64 voxels; thread -> (row, 32-voxel half).  The next
     // stage is loaded into registers while the current one is multiplied.
     const int lrow = threadIdx.x >> 1, lh = threadIdx.x & 1;
-    const bool lact = lrow < (diag ? GR : 2 * GR);
-    const int frame = lrow < GR ? gi * GR + lrow : gj * GR + (lrow - GR);
+    const int lblk = a.tab.blk[grp][lrow / GT];
+    const bool lact = lblk != 255;
+    const int frame = lblk * GT + lrow % GT;
     const bool fvalid = lact && frame < a.nt;
     const float2* srow = a.iq + (int64_t)(fvalid ? frame : 0) * a.nv;
     float re[32], im[32];
@@ -271,17 +273,78 @@ __global__ void gram_reduce_kernel(const ReduceArgs a) {
 }
 
 struct Plan {
-    int nb, ntiles, nbg, ngroups, nsplit;
+    int nb, ntiles, ngroups, nsplit;
     int64_t chunk;
     size_t bytes;
+    GroupTab tab;
 };
+
+// Tiles (I <= J) into groups of four that read at most four frame blocks: first every full
+// 2x2 block of tiles off the diagonal between the block pairs (2a, 2a+1) and (2b, 2b+1), then
+// the remaining tiles in row-major order, each group seeded with the first left and grown by
+// the tile that adds the fewest new blocks.  This reaches ceil(ntiles / 4) groups for every
+// nb <= 16 (a 2x2 tiling of the triangle needs up to 36% more, its diagonal and edge groups
+// being partly empty).
+void group_tiles(int nb, Plan& p) {
+    std::memset(&p.tab, 255, sizeof(p.tab));
+    std::vector<std::pair<int, int>> rest;
+    std::vector<char> used(nb * nb, 0);
+    int g = 0;
+    auto put = [&](int gi, const std::vector<std::pair<int, int>>& ts) {
+        int nbk = 0;
+        for (size_t w = 0; w < ts.size(); ++w) {
+            p.tab.ij[gi][w][0] = (unsigned char)ts[w].first;
+            p.tab.ij[gi][w][1] = (unsigned char)ts[w].second;
+            for (int x : {ts[w].first, ts[w].second}) {
+                bool have = false;
+                for (int k = 0; k < nbk; ++k) have |= p.tab.blk[gi][k] == x;
+                if (!have) p.tab.blk[gi][nbk++] = (unsigned char)x;
+            }
+        }
+    };
+    for (int a2 = 0; a2 + 1 < nb; a2 += 2)
+        for (int b2 = a2 + 2; b2 + 1 < nb; b2 += 2) {
+            const std::vector<std::pair<int, int>> ts = {{a2, b2}, {a2, b2 + 1}, {a2 + 1, b2}, {a2 + 1, b2 + 1}};
+            for (auto& t : ts) used[t.first * nb + t.second] = 1;
+            put(g++, ts);
+        }
+    for (int I = 0; I < nb; ++I)
+        for (int J = I; J < nb; ++J)
+            if (!used[I * nb + J]) rest.push_back({I, J});
+    while (!rest.empty()) {
+        std::vector<std::pair<int, int>> ts = {rest.front()};
+        rest.erase(rest.begin());
+        std::vector<int> blocks = {ts[0].first};
+        if (ts[0].second != ts[0].first) blocks.push_back(ts[0].second);
+        while (ts.size() < 4) {
+            int best = -1, best_add = 3;
+            for (size_t c = 0; c < rest.size(); ++c) {
+                int add = 0;
+                for (int x : {rest[c].first, rest[c].second}) {
+                    if (std::find(blocks.begin(), blocks.end(), x) == blocks.end()) ++add;
+                }
+                if (rest[c].first == rest[c].second && add == 2) add = 1;
+                if ((int)blocks.size() + add <= 4 && add < best_add) {
+                    best = (int)c;
+                    best_add = add;
+                }
+            }
+            if (best < 0) break;
+            for (int x : {rest[best].first, rest[best].second})
+                if (std::find(blocks.begin(), blocks.end(), x) == blocks.end()) blocks.push_back(x);
+            ts.push_back(rest[best]);
+            rest.erase(rest.begin() + best);
+        }
+        put(g++, ts);
+    }
+    p.ngroups = g;
+}
 
 Plan plan(int64_t nv, int nt, size_t max_bytes = 0) {
     Plan p{};
     p.nb = (nt + GT - 1) / GT;
     p.ntiles = p.nb * (p.nb + 1) / 2;
-    p.nbg = (p.nb + GG - 1) / GG;
-    p.ngroups = p.nbg * (p.nbg + 1) / 2;
+    group_tiles(p.nb, p);
     // about 2048 workgroups; voxel ranges are whole multiples of the 4096-voxel block
     int64_t want = std::max<int64_t>(1, 2048 / p.ngroups);
     if (max_bytes) {
@@ -339,8 +402,8 @@ int launch_gram(const float* iq, int64_t n_vox, int32_t n_t, int32_t gram_mode, 
     ga.nb = p.nb;
     ga.ntiles = p.ntiles;
     ga.nsplit = p.nsplit;
-    ga.nbg = p.nbg;
     ga.ngroups = p.ngroups;
+    ga.tab = p.tab;
     const unsigned nwg = (unsigned)(p.ngroups * p.nsplit);
     switch (gram_mode) {
         case FQ_GRAM_FP32:

@@ -149,3 +149,29 @@ def test_pd_alone_matches_explicit_projection(gpu, nt, K):
     print(f'pd rel L2: alone {e_alone:.2e} explicit {e_expl:.2e} alone vs explicit {e_pair:.2e}')
     assert e_alone < 1e-3 and e_expl < 1e-3 and e_pair < 1e-3
     assert (outs[0] >= 0).all()
+
+
+@pytest.mark.parametrize('nt', [33, 65, 97, 200, 225, 300, 512])
+@pytest.mark.parametrize('mode', [0, 3])
+def test_gram_tile_groups(gpu, nt, mode):
+    """The Gram's 32x32 tiles are dealt to workgroups in groups of four that read at most four
+    frame blocks (2, 3, 4, 7, 8, 10 and 16 blocks here): every tile of the Hermitian result,
+    against the FP64 oracle, on a voxel count ragged against the 4096-voxel ranges."""
+    import torch
+    print('gram tile groups n_t', nt, 'mode', mode, flush=True)
+    nv = 12289
+    iq = random_casorati(nv, nt, seed=nt + mode, rank=6, tissue_db=45)
+    G = torch.empty((nt, nt), dtype=torch.complex128, device='cuda')
+    ws = torch.empty(gpu.gram_workspace_size(nv, nt, mode), dtype=torch.uint8, device='cuda')
+    gpu.casorati_gram(dev(iq), G, ws, mode)
+    Gg = G.cpu().numpy()
+    Go = clutter.gram(iq)
+    err = rel_l2(Gg, Go)
+    print('gram rel L2', err)
+    assert err < 1e-6
+    np.testing.assert_array_equal(Gg, Gg.conj().T)
+    # every tile carries data: no 32x32 block of the result is off by more than the tolerance
+    for I in range(0, nt, 32):
+        for J in range(I, nt, 32):
+            blk, ref = Gg[I:I + 32, J:J + 32], Go[I:I + 32, J:J + 32]
+            assert np.linalg.norm(blk - ref) <= 1e-5 * np.linalg.norm(Go) + 1e-6 * np.linalg.norm(ref)
