@@ -625,10 +625,35 @@ def workload_run(cfg, steps, warmup, args, fq, torch, dev, filt, train, full=Tru
         'learned': timed(lambda: filt.infer(iq, pd_lcf)),
     }
     out['pd_volumes_per_s'] = {k: 1e3 / v for k, v in alone_ms.items()}
+
+    # a stream of ensembles: the same SVD path on two streams, volumes alternating, so one
+    # volume's single-workgroup eigensolver runs beside the next volume's Gram
+    def two_in_flight(mode, reps=8):
+        sets = [(G, gws, sws, sigma, k1, st1, pd_svd), (G2, gws2, sws2, sigma2, k2, st2, pd_split)]
+        strs = (torch.cuda.Stream(), torch.cuda.Stream())
+
+        def run(n):
+            for v in range(n):
+                Gx, gx, sx, sg, kx, stx, pdx = sets[v % 2]
+                with torch.cuda.stream(strs[v % 2]):
+                    fq.casorati_gram(iq, Gx, gx, mode)
+                    fq.svd_clutter_filter(iq, Gx, sx, sg, kx, cfg.cutoff, pd=pdx, status=stx)
+
+        run(2)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        run(reps)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / reps
+
+    out['pd_volumes_per_s_two_in_flight'] = {'svd_fp32': 1e3 / two_in_flight(fq.GRAM_FP32),
+                                              'svd_split4_bf16': 1e3 / two_in_flight(fq.GRAM_SPLIT4_BF16)}
     out['pd_volumes_per_s_note'] = ('each path timed alone on one stream (mean of 5 after a warm-up): Gram + '
                                     'eigendecomposition + cutoff + fused projection and PD, or learned inference '
-                                    'with PD; pd_volumes_per_s_in_step: the same stages inside the step, beside '
-                                    'the other two filters')
+                                    'with PD; pd_volumes_per_s_two_in_flight: a stream of ensembles, the SVD path '
+                                    'on two streams with volumes alternating (8 volumes, wall clock), one '
+                                    "volume's eigensolver beside the next one's Gram; pd_volumes_per_s_in_step: "
+                                    'the same stages inside the step, beside the other two filters')
     fq.lcf_fallback(pd_lcf, pd_svd, pd_out, fb_flag, fb_d, fb_ws, -10.0)
     out['learned_fallback'] = {'flag': int(fb_flag.item()), 'discrepancy_db_vs_svd': float(fb_d.item())}
 

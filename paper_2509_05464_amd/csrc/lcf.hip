@@ -59,7 +59,8 @@ __device__ __forceinline__ float gelu_fwd(float z) {
     poly = fmaf(poly, t, -0.142248368f);
     poly = fmaf(poly, t, 0.127414796f);
     const float e = __builtin_amdgcn_exp2f((z * -0.72134752044448170f) * z);   // exp(-z^2 / 2)
-    return fmaf(-az, poly * t * e, fmaxf(z, 0.0f));
+    // max(z, 0) on the bit pattern: one integer max, no NaN-quieting of the float max
+    return fmaf(-az, poly * t * e, __int_as_float(max(__float_as_int(z), 0)));
 }
 // two floats to BF16 (round to nearest even) with the hardware pair conversion
 __device__ __forceinline__ unsigned int f2bf2(float lo, float hi) {
