@@ -345,8 +345,9 @@ Plan plan(int64_t nv, int nt, size_t max_bytes = 0) {
     p.nb = (nt + GT - 1) / GT;
     p.ntiles = p.nb * (p.nb + 1) / 2;
     group_tiles(p.nb, p);
-    // about 2048 workgroups; voxel ranges are whole multiples of the 4096-voxel block
-    int64_t want = std::max<int64_t>(1, 2048 / p.ngroups);
+    // about 8192 workgroups (short voxel ranges: the groups of one range stay close enough
+    // in step to share its stages through the L2); ranges are whole multiples of 4096 voxels
+    int64_t want = std::max<int64_t>(1, 8192 / p.ngroups);
     if (max_bytes) {
         // at most max_bytes of partial tiles: whole multiples of NXCD voxel ranges
         const size_t per_split = (size_t)p.ntiles * 2 * GT * GT * sizeof(double);
