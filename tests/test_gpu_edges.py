@@ -78,6 +78,24 @@ def test_gram_eig_small_and_odd_ensembles(gpu, nt):
     np.testing.assert_allclose((V * lam.cpu().numpy()) @ V.conj().T, Go, atol=1e-9 * np.abs(Go).max())
 
 
+
+@pytest.mark.parametrize('nv,nt', [(1, 5), (63, 40), (4097, 70), (9001, 33), (12289, 7)])
+def test_gram_ragged_and_odd_voxel_counts(gpu, nv, nt):
+    """Voxel counts that leave a partial 64-voxel stage, odd counts (rows not 16-byte
+    aligned: the element-wise loads) and counts over several 4096-voxel ranges, in every
+    Gram mode: FP32 against the FP64 Gram, the BF16 modes against their bit-exact
+    emulation."""
+    import torch
+    from oracle import bf16 as obf16
+    iq = random_casorati(nv, nt, seed=nv + nt, rank=min(3, nt)).astype(np.complex64)
+    x = dev(iq)
+    for mode, want in ((0, clutter.gram(iq)), (1, obf16.gram_split_bf16(iq, 3)),
+                       (2, obf16.gram_split_bf16(iq, 1)), (3, obf16.gram_split_bf16(iq, 4))):
+        ws = torch.empty(max(1, gpu.gram_workspace_size(nv, nt, mode)), dtype=torch.uint8, device='cuda')
+        G = torch.empty((nt, nt), dtype=torch.complex128, device='cuda')
+        gpu.casorati_gram(x, G, ws, mode)
+        assert rel_l2(G.cpu().numpy(), want) < 1e-6, mode
+
 def test_full_cutoff_removes_everything(gpu):
     iq = random_casorati(2000, 12, seed=5).astype(np.complex64)
     out = gpu_svd_pd(dev(iq), 12)
