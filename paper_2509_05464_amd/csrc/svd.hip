@@ -211,7 +211,7 @@ __global__ void __launch_bounds__(TRI_THREADS) tridiag_kernel(const TriArgs a) {
 // Register-resident form for n <= RT_N: the lower triangle of A (the Hermitian matrix) is
 // held in the registers of one workgroup for the whole reduction, so a step reads and
 // writes no global memory.  The triangle is cut into 16x16 blocks (I >= J), listed by
-// block column J descending and I ascending and dealt to the 16 wavefronts in turn (a
+// block column J descending and I ascending and dealt to the 8 wavefronts in turn (a
 // wavefront keeps blocks across the whole matrix, so the shrinking trailing block stays
 // spread over all of them); in a block, lane l holds rows 4(l/16) .. 4(l/16)+3 of column
 // l%16.  Step k:
@@ -225,9 +225,11 @@ __global__ void __launch_bounds__(TRI_THREADS) tridiag_kernel(const TriArgs a) {
 //   5. A22 -= v w^H + w v^H on the stored elements with j > k.
 // v and p alternate between two buffers by step parity, so a step's writes never meet
 // the previous step's reads (three barriers per step).
-constexpr int RT_N = 208;                  // 13 block rows: 91 blocks, at most 6 per wavefront
-constexpr int RT_BPW = 6;                  // blocks per wavefront
-constexpr int RT_REG = 4;                  // of them in registers; the rest in LDS (lane-private)
+constexpr int RT_N = 208;                  // 13 block rows: 91 blocks, at most 12 per wavefront
+constexpr int RT_THREADS = 512;            // 8 wavefronts, 2 per SIMD: 256 registers each
+constexpr int RT_WAVES = RT_THREADS / 64;
+constexpr int RT_BPW = 12;                 // blocks per wavefront
+constexpr int RT_REG = 8;                  // of them in registers; the rest in LDS (lane-private)
 
 __device__ __forceinline__ void rt_block(int b, int nbr, int& I, int& J) {
     I = J = -1;
@@ -320,17 +322,17 @@ __device__ __forceinline__ void rt_update(double2 (&x)[4], int i0, int j, int n,
     }
 }
 
-__global__ void __launch_bounds__(TRI_THREADS) tridiag_reg_kernel(const TriArgs a) {
+__global__ void __launch_bounds__(RT_THREADS) tridiag_reg_kernel(const TriArgs a) {
     __shared__ double2 col[RT_N];
     __shared__ double2 sv[2][RT_N], sp[2][RT_N];
     __shared__ double2 s_tau;
     // blocks RT_REG .. RT_BPW-1 of each wavefront: [wave][block][q][lane]
-    __shared__ double2 AL[(TRI_THREADS / 64) * (RT_BPW - RT_REG) * 4 * 64];
+    __shared__ double2 AL[RT_WAVES * (RT_BPW - RT_REG) * 4 * 64];
     const int n = a.n, tid = threadIdx.x, lane = tid & 63;
     const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);   // uniform: block bookkeeping in scalars
     const int nbr = (n + 15) / 16;
     const int c = lane & 15, rb = (lane >> 4) * 4;
-    for (int i = tid; i < RT_N; i += TRI_THREADS) {
+    for (int i = tid; i < RT_N; i += RT_THREADS) {
         col[i] = sv[0][i] = sv[1][i] = sp[0][i] = sp[1][i] = make_double2(0.0, 0.0);
     }
     auto lds_blk = [&](int s, int q) -> double2& { return AL[((wv * (RT_BPW - RT_REG) + s - RT_REG) * 4 + q) * 64 + lane]; };
@@ -338,7 +340,7 @@ __global__ void __launch_bounds__(TRI_THREADS) tridiag_reg_kernel(const TriArgs 
     double2 A[RT_REG][4];
 #pragma unroll
     for (int s = 0; s < RT_BPW; ++s) {
-        rt_block(wv + 16 * s, nbr, bI[s], bJ[s]);
+        rt_block(wv + RT_WAVES * s, nbr, bI[s], bJ[s]);
         const int j = 16 * bJ[s] + c;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
@@ -369,7 +371,7 @@ __global__ void __launch_bounds__(TRI_THREADS) tridiag_reg_kernel(const TriArgs 
                 }
             }
         }
-        for (int i = tid; i < n; i += TRI_THREADS) p[i] = make_double2(0.0, 0.0);
+        for (int i = tid; i < n; i += RT_THREADS) p[i] = make_double2(0.0, 0.0);
         __syncthreads();
         // 2. the reflector of column k
         if (wv == 0) {
@@ -1288,6 +1290,7 @@ __global__ void __launch_bounds__(256) pd_kernel(const float2* iq, int64_t nv, i
 }
 
 using TriFn = void (*)(const TriArgs);
+int tri_threads(int n) { return n <= RT_N ? RT_THREADS : TRI_THREADS; }
 TriFn tri_fn(int n) {
     if (n <= RT_N) return tridiag_reg_kernel;
     if (n <= 256) return tridiag_kernel<4>;
@@ -1350,7 +1353,7 @@ int launch_eig(const double* gram, int n, char* ws, const SvdWs& L, double* lam,
     double* Zs = reinterpret_cast<double*>(ws + L.off_Zs);
 
     TriArgs ta{reinterpret_cast<const double2*>(gram), reinterpret_cast<double2*>(ws + L.off_A), vh, tau, d, e, n};
-    hipLaunchKernelGGL(tri_fn(n), dim3(1), dim3(TRI_THREADS), 0, s, ta);
+    hipLaunchKernelGGL(tri_fn(n), dim3(1), dim3(tri_threads(n)), 0, s, ta);
     FQ_LAUNCH_CHECK();
     QlArgs qa{d, e, ri, rc, rs, rn, L.cap, lam, sigma, perm, status, n};
     hipLaunchKernelGGL(ql_kernel, dim3(1), dim3(64), 0, s, qa);
@@ -1373,7 +1376,7 @@ int launch_eigvals(const double* gram, int n, char* ws, const SvdWs& L, double* 
     TriArgs ta{reinterpret_cast<const double2*>(gram), reinterpret_cast<double2*>(ws + L.off_A),
                reinterpret_cast<double2*>(ws + L.off_vh), reinterpret_cast<double2*>(ws + L.off_tau),
                reinterpret_cast<double*>(ws + L.off_d), reinterpret_cast<double*>(ws + L.off_e), n};
-    hipLaunchKernelGGL(tri_fn(n), dim3(1), dim3(TRI_THREADS), 0, s, ta);
+    hipLaunchKernelGGL(tri_fn(n), dim3(1), dim3(tri_threads(n)), 0, s, ta);
     FQ_LAUNCH_CHECK();
     EigvalArgs ea{reinterpret_cast<const double*>(ws + L.off_d), reinterpret_cast<const double*>(ws + L.off_e),
                   reinterpret_cast<double*>(ws + L.off_ev), reinterpret_cast<double*>(ws + L.off_sc), lam, sigma,
