@@ -252,24 +252,44 @@ struct ReduceArgs {
     int nt, nb, ntiles, nsplit;
 };
 
-__global__ void gram_reduce_kernel(const ReduceArgs a) {
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= a.nt * a.nt) return;
-    const int f = idx / a.nt, g = idx % a.nt;
-    const int lo = min(f, g), hi = max(f, g);
-    const int I = lo / GT, J = hi / GT;
-    // tile index of (I, J) in the row-major upper triangle
-    const int t = I * a.nb - I * (I - 1) / 2 + (J - I);
-    const int i = lo % GT, j = hi % GT;
-    double re = 0.0, im = 0.0;
-    for (int s = 0; s < a.nsplit; ++s) {
-        const double* p = a.part + ((int64_t)s * a.ntiles + t) * 2 * GT * GT + i * GT + j;
-        re += p[0];
-        im += p[GT * GT];
+// One thread per element of the partial tiles and per eighth of the voxel ranges (consecutive
+// threads read consecutive words of each range's tiles); the eight part sums are added in a
+// fixed order (deterministic).  Tile element (i, j) of tile (I, J) is G[f][g], f = 32 I + i,
+// g = 32 J + j; elements with f < g are written with their mirror conj(G[f][g]) at G[g][f], the
+// diagonal with a zero imaginary part, and the lower half of the diagonal tiles is not read.
+constexpr int RED_GROUPS = 8;
+__global__ void __launch_bounds__(256) gram_reduce_kernel(const ReduceArgs a) {
+    __shared__ double sums[RED_GROUPS][32];
+    const int le = threadIdx.x % 32, rg = threadIdx.x / 32;
+    const int64_t per_split = (int64_t)a.ntiles * 2 * GT * GT;
+    const int64_t e = (int64_t)blockIdx.x * 32 + le;
+    double acc = 0.0;
+    if (e < per_split)
+        for (int sp = rg; sp < a.nsplit; sp += RED_GROUPS) acc += a.part[(int64_t)sp * per_split + e];
+    sums[rg][le] = acc;
+    __syncthreads();
+    if (rg != 0 || e >= per_split) return;
+    double tot = sums[0][le];
+#pragma unroll
+    for (int q = 1; q < RED_GROUPS; ++q) tot += sums[q][le];
+    int t = (int)(e / (2 * GT * GT));
+    const int rem = (int)(e % (2 * GT * GT));
+    const int c = rem / (GT * GT), i = (rem % (GT * GT)) / GT, j = rem % GT;
+    int I = 0;
+    while (t >= a.nb - I) {   // tile t of the row-major upper triangle -> (I, J)
+        t -= a.nb - I;
+        ++I;
     }
-    if (f == g) im = 0.0;
-    if (f > g) im = -im;
-    a.gram[idx] = make_double2(re, im);
+    const int J = I + t;
+    const int f = I * GT + i, g = J * GT + j;
+    if (f >= a.nt || g >= a.nt || f > g) return;
+    double* G = reinterpret_cast<double*>(a.gram);   // [nt][nt] x (Re, Im)
+    if (f == g) {
+        G[((int64_t)f * a.nt + g) * 2 + c] = c ? 0.0 : tot;
+        return;
+    }
+    G[((int64_t)f * a.nt + g) * 2 + c] = tot;
+    G[((int64_t)g * a.nt + f) * 2 + c] = c ? -tot : tot;
 }
 
 struct Plan {
@@ -423,8 +443,8 @@ int launch_gram(const float* iq, int64_t n_vox, int32_t n_t, int32_t gram_mode, 
     FQ_LAUNCH_CHECK();
     ReduceArgs ra{reinterpret_cast<const double*>(ws), reinterpret_cast<double2*>(gram), n_t, p.nb, p.ntiles,
                   p.nsplit};
-    const int n2 = n_t * n_t;
-    hipLaunchKernelGGL(gram_reduce_kernel, dim3((n2 + 255) / 256), dim3(256), 0, s, ra);
+    const int64_t per_split = (int64_t)p.ntiles * 2 * GT * GT;
+    hipLaunchKernelGGL(gram_reduce_kernel, dim3((unsigned)((per_split + 31) / 32)), dim3(256), 0, s, ra);
     FQ_LAUNCH_CHECK();
     return FQ_OK;
 }
