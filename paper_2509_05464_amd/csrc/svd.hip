@@ -257,6 +257,22 @@ constexpr int DPP_XOR1 = 0xB1;       // quad_perm [1, 0, 3, 2]
 constexpr int DPP_XOR2 = 0x4E;       // quad_perm [2, 3, 0, 1]
 constexpr int DPP_ROR4 = 0x124, DPP_ROR8 = 0x128, DPP_ROR12 = 0x12C;
 
+// value of lane l (l uniform), the same in every lane
+__device__ __forceinline__ double lane_f64(double x, int l) {
+    const long long u = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_readlane((int)u, l), hi = __builtin_amdgcn_readlane((int)(u >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+// sum over a full wavefront, the same value in every lane: each row of 16 lanes summed by
+// DPP (quad swaps, then rotations by 4 and 8), the four row totals read out in a fixed order
+__device__ __forceinline__ double wave_total(double x) {
+    x += dpp_f64<DPP_XOR1>(x);
+    x += dpp_f64<DPP_XOR2>(x);
+    x += dpp_f64<DPP_ROR4>(x);
+    x += dpp_f64<DPP_ROR8>(x);
+    return (lane_f64(x, 0) + lane_f64(x, 16)) + (lane_f64(x, 32) + lane_f64(x, 48));
+}
+
 // step 3 on one block (rows i0 .. i0+3 of column j in this lane)
 __device__ __forceinline__ void rt_matvec(const double2 (&x)[4], int i0, int j, int n, int c, int lane,
                                           const double2* v, double2* p) {
@@ -377,13 +393,7 @@ __global__ void __launch_bounds__(RT_THREADS) tridiag_reg_kernel(const TriArgs a
         if (wv == 0) {
             double ps = 0.0;
             for (int i = k + 2 + lane; i < n; i += 64) ps += col[i].x * col[i].x + col[i].y * col[i].y;
-            ps += dpp_f64<DPP_XOR1>(ps);
-            ps += dpp_f64<DPP_XOR2>(ps);
-            ps += dpp_f64<DPP_ROR4>(ps);   // then lanes x and x - 4 of the row summed
-            ps += dpp_f64<DPP_ROR8>(ps);   // and x - 8, x - 12: the row's total
-            ps += __shfl_xor(ps, 16);
-            ps += __shfl_xor(ps, 32);
-            const double sigma = ps;
+            const double sigma = wave_total(ps);
             const double2 alpha = col[k + 1];
             double2 tau = make_double2(0.0, 0.0), scale = make_double2(0.0, 0.0);
             double beta = alpha.x;
@@ -429,7 +439,7 @@ __global__ void __launch_bounds__(RT_THREADS) tridiag_reg_kernel(const TriArgs a
         // 4. r = v^H p (real), in every wavefront
         double pr = 0.0;
         for (int i = k + 1 + lane; i < n; i += 64) pr += v[i].x * p[i].x + v[i].y * p[i].y;
-        for (int o = 32; o > 0; o >>= 1) pr += __shfl_xor(pr, o);
+        pr = wave_total(pr);
         const double hw = 0.5 * (tau.x * tau.x + tau.y * tau.y) * pr;
         // 5. the rank-2 update on columns beyond k
 #pragma unroll
@@ -991,33 +1001,39 @@ __global__ void __launch_bounds__(64) back_kernel(const BackArgs a) {
         const int i = lane + 64 * t;
         z[t] = make_double2(i < n ? a.Z[(size_t)i * a.zr + (size_t)j * a.zc] : 0.0, 0.0);
     }
-    for (int k = n - 2; k >= 0; --k) {
-        const double2 tau = a.tau[k];
-        if (tau.x == 0.0 && tau.y == 0.0) continue;
+    // reflector k's tau and v (zero outside rows k+1 .. n-1), fetched one reflector ahead
+    double2 vn[BT_PER_LANE], taun = make_double2(0.0, 0.0);
+    auto fetch = [&](int k) {
+        taun = a.tau[k];
         const double2* v = a.vh + (size_t)k * n;
+#pragma unroll
+        for (int t = 0; t < BT_PER_LANE; ++t) {
+            const int i = lane + 64 * t;
+            vn[t] = i > k && i < n ? v[i] : make_double2(0.0, 0.0);
+        }
+    };
+    if (n >= 2) fetch(n - 2);
+    for (int k = n - 2; k >= 0; --k) {
+        double2 v[BT_PER_LANE];
+#pragma unroll
+        for (int t = 0; t < BT_PER_LANE; ++t) v[t] = vn[t];
+        const double2 tau = taun;
+        if (k > 0) fetch(k - 1);
+        if (tau.x == 0.0 && tau.y == 0.0) continue;
         double2 dot = make_double2(0.0, 0.0);   // v^H z over rows k+1 .. n-1
 #pragma unroll
         for (int t = 0; t < BT_PER_LANE; ++t) {
-            const int i = lane + 64 * t;
-            if (i > k && i < n) {
-                const double2 vi = v[i];
-                dot.x += vi.x * z[t].x + vi.y * z[t].y;
-                dot.y += vi.x * z[t].y - vi.y * z[t].x;
-            }
+            dot.x += v[t].x * z[t].x + v[t].y * z[t].y;
+            dot.y += v[t].x * z[t].y - v[t].y * z[t].x;
         }
-        for (int o = 32; o > 0; o >>= 1) {
-            dot.x += __shfl_xor(dot.x, o);
-            dot.y += __shfl_xor(dot.y, o);
-        }
+        dot.x = wave_total(dot.x);
+        dot.y = wave_total(dot.y);
         const double2 td = zmul(tau, dot);
 #pragma unroll
         for (int t = 0; t < BT_PER_LANE; ++t) {
-            const int i = lane + 64 * t;
-            if (i > k && i < n) {
-                const double2 u = zmul(v[i], td);
-                z[t].x -= u.x;
-                z[t].y -= u.y;
-            }
+            const double2 u = zmul(v[t], td);
+            z[t].x -= u.x;
+            z[t].y -= u.y;
         }
     }
 #pragma unroll
