@@ -263,6 +263,19 @@ __device__ __forceinline__ double lane_f64(double x, int l) {
     const int lo = __builtin_amdgcn_readlane((int)u, l), hi = __builtin_amdgcn_readlane((int)(u >> 32), l);
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
+// x + x(lane ^ 16) and x + x(lane ^ 32), the same value in both lanes of each pair: the
+// gfx950 row swaps (permlane16_swap of x with itself gives the even rows' values in the first
+// result and the odd rows' in the second, permlane32_swap the lower and upper halves')
+template <bool HALVES>
+__device__ __forceinline__ double swap_sum(double x) {
+    const long long u = __double_as_longlong(x);
+    const int lo = (int)u, hi = (int)(u >> 32);
+    auto l = HALVES ? __builtin_amdgcn_permlane32_swap(lo, lo, false, false) : __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+    auto h = HALVES ? __builtin_amdgcn_permlane32_swap(hi, hi, false, false) : __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+    const double a = __longlong_as_double(((long long)h[0] << 32) | (unsigned int)l[0]);
+    const double b = __longlong_as_double(((long long)h[1] << 32) | (unsigned int)l[1]);
+    return a + b;
+}
 // sum over a full wavefront, the same value in every lane: each row of 16 lanes summed by
 // DPP (quad swaps, then rotations by 4 and 8), the four row totals read out in a fixed order
 __device__ __forceinline__ double wave_total(double x) {
@@ -310,10 +323,8 @@ __device__ __forceinline__ void rt_matvec(const double2 (&x)[4], int i0, int j, 
         atomicAdd(reinterpret_cast<double*>(p + i0 + (idx >> 1)) + (idx & 1), e1);
     }
     // column sums over the block's 4 row groups
-    cs.x += __shfl_xor(cs.x, 16);
-    cs.y += __shfl_xor(cs.y, 16);
-    cs.x += __shfl_xor(cs.x, 32);
-    cs.y += __shfl_xor(cs.y, 32);
+    cs.x = swap_sum<true>(swap_sum<false>(cs.x));
+    cs.y = swap_sum<true>(swap_sum<false>(cs.y));
     if (lane < 16 && j < n) {
         atomicAdd(&p[j].x, cs.x);
         atomicAdd(&p[j].y, cs.y);
