@@ -10,7 +10,9 @@ component.  Input x = [Re, Im](S[v, :]) / s_v with s_v = sqrt(mean_f |S[v,f]|^2 
     h3 = GELU(conv9(h2; W3[32,32,9], b3))
     y  = conv1(h3; W4[2,32], b4)
 conv9(z)[o,t] = b[o] + sum_i sum_{k=0..8} W[o,i,k] z[i, t+k-4] with zeros outside
-[0, T) ("same" padding); GELU(z) = z/2 (1 + erf(z/sqrt 2)).
+[0, T) ("same" padding); GELU in its tanh form (Hendrycks & Gimpel),
+    GELU(z) = z/2 (1 + tanh(sqrt(2/pi) (z + 0.044715 z^3))),
+which stays within 4.8e-4 of the erf form z/2 (1 + erf(z/sqrt 2)).
 Blood estimate S_b[v,f] = s_v (y0 + i y1); loss = mean over (n, channel, t) of
 (y - y_target)^2 with y_target = [Re, Im](S_blood[v,:]) / s_v.
 
@@ -30,7 +32,6 @@ from __future__ import annotations
 from typing import Dict, Tuple
 
 import numpy as np
-from scipy.special import erf
 
 from .bf16 import bf16_round
 
@@ -55,12 +56,18 @@ def pack(p: Dict[str, np.ndarray]) -> np.ndarray:
     return np.concatenate([np.asarray(p[name], dtype=np.float64).ravel() for name, _ in SHAPES])
 
 
+GELU_C = np.sqrt(2.0 / np.pi)
+GELU_A = 0.044715
+
+
 def gelu(z):
-    return 0.5 * z * (1.0 + erf(z / np.sqrt(2.0)))
+    return 0.5 * z * (1.0 + np.tanh(GELU_C * (z + GELU_A * z ** 3)))
 
 
 def gelu_grad(z):
-    return 0.5 * (1.0 + erf(z / np.sqrt(2.0))) + z * np.exp(-0.5 * z * z) / np.sqrt(2.0 * np.pi)
+    """d GELU / dz: (1 + tanh u)/2 + z (1 - tanh^2 u) u'/2, u = C (z + A z^3)."""
+    th = np.tanh(GELU_C * (z + GELU_A * z ** 3))
+    return 0.5 * (1.0 + th) + 0.5 * z * (1.0 - th * th) * GELU_C * (1.0 + 3.0 * GELU_A * z * z)
 
 
 def conv(z: np.ndarray, W: np.ndarray, b: np.ndarray) -> np.ndarray:

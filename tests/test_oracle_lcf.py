@@ -14,9 +14,9 @@ def _torch_forward(w, x):
     for v in p.values():
         v.requires_grad_(True)
     xt = torch.tensor(x, dtype=torch.float64)
-    h = Fn.gelu(Fn.conv1d(xt, p['W1'], p['b1'], padding=4))
-    h = Fn.gelu(Fn.conv1d(h, p['W2'], p['b2'], padding=4))
-    h = Fn.gelu(Fn.conv1d(h, p['W3'], p['b3'], padding=4))
+    h = Fn.gelu(Fn.conv1d(xt, p['W1'], p['b1'], padding=4), approximate='tanh')
+    h = Fn.gelu(Fn.conv1d(h, p['W2'], p['b2'], padding=4), approximate='tanh')
+    h = Fn.gelu(Fn.conv1d(h, p['W3'], p['b3'], padding=4), approximate='tanh')
     y = Fn.conv1d(h, p['W4'][:, :, None], p['b4'])
     return y, p
 
@@ -137,3 +137,18 @@ def test_bf16_input_as_two_terms():
     e_two = np.linalg.norm(lcf._q2(s, True) - s) / np.linalg.norm(small)
     e_one = np.linalg.norm(lcf._q(s, True) - s) / np.linalg.norm(small)
     assert e_two < 1e-2 and e_one > 0.5
+
+
+def test_gelu_tanh_form_against_torch():
+    """The activation and its derivative against torch's tanh-form GELU (value and
+    autograd derivative), GELU(0) = 0 and GELU'(0) = 1/2, and the tanh form within
+    4.8e-4 of the erf form."""
+    from scipy.special import erf
+    z = np.linspace(-8.0, 8.0, 4001)
+    zt = torch.tensor(z, dtype=torch.float64, requires_grad=True)
+    y = Fn.gelu(zt, approximate='tanh')
+    y.sum().backward()
+    np.testing.assert_allclose(lcf.gelu(z), y.detach().numpy(), rtol=0, atol=1e-14)
+    np.testing.assert_allclose(lcf.gelu_grad(z), zt.grad.numpy(), rtol=0, atol=1e-13)
+    assert lcf.gelu(np.array([0.0]))[0] == 0.0 and abs(lcf.gelu_grad(np.array([0.0]))[0] - 0.5) < 1e-15
+    assert np.abs(lcf.gelu(z) - 0.5 * z * (1.0 + erf(z / np.sqrt(2.0)))).max() < 4.8e-4
