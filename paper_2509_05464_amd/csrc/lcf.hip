@@ -45,22 +45,15 @@ __device__ __forceinline__ unsigned short f2bf(float x) {
     return (unsigned short)(u >> 16);
 }
 __device__ __forceinline__ float bf2f(unsigned short b) { return __uint_as_float((unsigned int)b << 16); }
-__device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
-// GELU for the forward pass, whose result is rounded to BF16: erf by formula 7.1.26 of
-// Abramowitz & Stegun (Handbook of Mathematical Functions), |error| <= 1.5e-7,
-//   1 - erf(x) = t (a1 + t (a2 + t (a3 + t (a4 + t a5)))) exp(-x^2), t = 1/(1 + p x), x >= 0,
-// at x = |z|/sqrt 2.  With q = (1 - erf(x))/2 (the a_i halved),
-//   GELU(z) = z (1 + sign(z) erf(x))/2 = max(z, 0) - |z| q.
+// GELU in its tanh form (Hendrycks & Gimpel): GELU(z) = z (1 + tanh u)/2, u = C (z + A z^3),
+// C = sqrt(2/pi), A = 0.044715.  With (1 + tanh u)/2 = 1/(1 + exp(-2u)) and exp(-2u) =
+// 2^(z (K1 + K3 z^2)), K1 = -2 C log2 e, K3 = -2 C A log2 e: three multiply/FMAs, one
+// exponential, one add, one reciprocal and a product (z -> -inf: 2^y overflows, the
+// reciprocal gives 0 and GELU -0; z -> +inf: GELU = z).
+constexpr float GELU_K1 = -2.3022081982f, GELU_K3 = -0.10294324f;
 __device__ __forceinline__ float gelu_fwd(float z) {
-    const float az = fabsf(z);
-    const float t = __builtin_amdgcn_rcpf(fmaf(0.23164189f, az, 1.0f));   // p / sqrt 2
-    float poly = fmaf(0.5307027145f, t, -0.7265760135f);
-    poly = fmaf(poly, t, 0.7107068705f);
-    poly = fmaf(poly, t, -0.142248368f);
-    poly = fmaf(poly, t, 0.127414796f);
-    const float e = __builtin_amdgcn_exp2f((z * -0.72134752044448170f) * z);   // exp(-z^2 / 2)
-    // max(z, 0) on the bit pattern: one integer max, no NaN-quieting of the float max
-    return fmaf(-az, poly * t * e, __int_as_float(max(__float_as_int(z), 0)));
+    const float y = z * fmaf(GELU_K3, z * z, GELU_K1);
+    return z * __builtin_amdgcn_rcpf(__builtin_amdgcn_exp2f(y) + 1.0f);
 }
 // two floats to BF16 (round to nearest even) with the hardware pair conversion
 __device__ __forceinline__ unsigned int f2bf2(float lo, float hi) {
@@ -68,8 +61,11 @@ __device__ __forceinline__ unsigned int f2bf2(float lo, float hi) {
     const bf16x2 v = {(__bf16)lo, (__bf16)hi};
     return __builtin_bit_cast(unsigned int, v);
 }
+// d GELU / dz = s + 2 C z s (1 - s) (1 + 3 A z^2), s = (1 + tanh u)/2
 __device__ __forceinline__ float gelu_grad(float z) {
-    return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) + z * 0.39894228040143268f * expf(-0.5f * z * z);
+    const float z2 = z * z;
+    const float s = 1.0f / (1.0f + exp2f(z * fmaf(GELU_K3, z2, GELU_K1)));
+    return s + 1.5957691216f * z * s * (1.0f - s) * fmaf(0.134145f, z2, 1.0f);
 }
 __device__ __forceinline__ float wave_sum(float v) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
