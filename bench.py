@@ -220,6 +220,23 @@ def das_only(cfg, args, fq, torch, dev):
                       'tflops': DAS_FLOP_PER_UNIT * units / (ms / 1e3) / 1e12}))
 
 
+def capture_graph(fn, torch):
+    """fn (a clutter-filter path: kernel launches only, its size classes chosen on the device)
+    captured once as a HIP graph, after one run on a side stream; replaying it drops the launch
+    gaps between its dependent kernels."""
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        fn()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        fn()
+    torch.cuda.synchronize()
+    return g
+
+
 def filters_only(cfg, args, fq, torch, dev):
     """The three power-Doppler paths (FP32 SVD, four-product split-BF16 SVD, learned inference)
     on the workload's own ensemble (scene -> RF -> DAS, untimed), each run `steps` times after
@@ -273,6 +290,16 @@ def filters_only(cfg, args, fq, torch, dev):
         e1.record()
         torch.cuda.synchronize()
         out['ms_per_volume'][name] = e0.elapsed_time(e1) / max(1, args.steps)
+    out['ms_per_volume_graph'] = {}
+    for name in ('svd_fp32', 'svd_split4_bf16'):
+        g = capture_graph(paths[name], torch)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(args.steps):
+            g.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        out['ms_per_volume_graph'][name] = e0.elapsed_time(e1) / max(1, args.steps)
     out['k_used'] = int(k.item())
     print(json.dumps(out))
 
@@ -611,6 +638,9 @@ def workload_run(cfg, steps, warmup, args, fq, torch, dev, filt, train, full=Tru
         torch.cuda.synchronize()
         return a.elapsed_time(b) / reps
 
+    def graph_ms(fn, reps=5):
+        return timed(capture_graph(fn, torch).replay, reps)
+
     # PD volumes/s of each clutter-filter path on its own (one stream, nothing beside it):
     # ensemble IQ in HBM -> PD volume; in the step the three paths share the GPU
     _log(f'[bench] {cfg.name}: PD paths alone')
@@ -625,6 +655,11 @@ def workload_run(cfg, steps, warmup, args, fq, torch, dev, filt, train, full=Tru
         'learned': timed(lambda: filt.infer(iq, pd_lcf)),
     }
     out['pd_volumes_per_s'] = {k: 1e3 / v for k, v in alone_ms.items()}
+    out['pd_volumes_per_s_graph'] = {
+        'svd_fp32': 1e3 / graph_ms(svd_path(fq.GRAM_FP32, cfg.cutoff, G, sws, sigma, k1, pd_svd, st1)),
+        'svd_split4_bf16': 1e3 / graph_ms(svd_path(fq.GRAM_SPLIT4_BF16, cfg.cutoff, G2, sws2, sigma2, k2, pd_split,
+                                                   st2)),
+    }
 
     # a stream of ensembles: the same SVD path on two streams, volumes alternating, so one
     # volume's single-workgroup eigensolver runs beside the next volume's Gram
@@ -652,8 +687,10 @@ def workload_run(cfg, steps, warmup, args, fq, torch, dev, filt, train, full=Tru
                                     'eigendecomposition + cutoff + fused projection and PD, or learned inference '
                                     'with PD; pd_volumes_per_s_two_in_flight: a stream of ensembles, the SVD path '
                                     'on two streams with volumes alternating (8 volumes, wall clock), one '
-                                    "volume's eigensolver beside the next one's Gram; pd_volumes_per_s_in_step: "
-                                    'the same stages inside the step, beside the other two filters')
+                                    "volume's eigensolver beside the next one's Gram; pd_volumes_per_s_graph: the "
+                                    'SVD path captured once as a HIP graph and replayed (mean of 5); '
+                                    'pd_volumes_per_s_in_step: the same stages inside the step, beside the other '
+                                    'two filters')
     fq.lcf_fallback(pd_lcf, pd_svd, pd_out, fb_flag, fb_d, fb_ws, -10.0)
     out['learned_fallback'] = {'flag': int(fb_flag.item()), 'discrepancy_db_vs_svd': float(fb_d.item())}
 

@@ -220,7 +220,8 @@ __global__ void __launch_bounds__(TRI_THREADS) tridiag_kernel(const TriArgs a) {
 //   3. p = A22 v: each stored A_ij (i > j) adds A_ij v_j to p_i and conj(A_ij) v_i to p_j
 //      (the diagonal only the first): row sums are reduced over the block's 16 columns by
 //      a halving butterfly (each exchange halves the values a lane carries), column sums
-//      over its 4 row groups, both added into p with LDS atomics;
+//      over its 4 row groups, both added into p with LDS atomics (each contribution rounded
+//      to a grid on which the FP64 sums are exact: the reduction is deterministic);
 //   4. every wavefront forms r = v^H p itself, and w = tau p - |tau|^2 r v / 2 on the fly;
 //   5. A22 -= v w^H + w v^H on the stored elements with j > k.
 // v and p alternate between two buffers by step parity, so a step's writes never meet
@@ -286,9 +287,20 @@ __device__ __forceinline__ double wave_total(double x) {
     return (lane_f64(x, 0) + lane_f64(x, 16)) + (lane_f64(x, 32) + lane_f64(x, 48));
 }
 
+// p = A22 v is summed in LDS by FP64 atomics from the blocks of every wavefront in the order
+// they arrive.  Each contribution is first rounded to a multiple of delta = 1/scale: the
+// contributions to p_i are the block pieces of one row of the Hermitian trailing matrix times v,
+// so by Cauchy-Schwarz every partial sum of them is at most ||A_i|| ||v|| <= sqrt(2) ||A||_F
+// (||v||^2 <= 2; the trailing block keeps ||A||_F), below 2^53 delta for the scale chosen; every
+// FP64 addition is then exact and the sums do not depend on the order, so the reduction is
+// deterministic.  delta <= 2^-51 ||A||_F, a few units in the last place of the products' sums.
+__device__ __forceinline__ double quantize(double x, double scale, double inv_scale) {
+    return rint(x * scale) * inv_scale;
+}
+
 // step 3 on one block (rows i0 .. i0+3 of column j in this lane)
 __device__ __forceinline__ void rt_matvec(const double2 (&x)[4], int i0, int j, int n, int c, int lane,
-                                          const double2* v, double2* p) {
+                                          const double2* v, double2* p, double scale, double inv_scale) {
     const double2 vj = v[j];
     double d[8];
     double2 cs = make_double2(0.0, 0.0);
@@ -320,14 +332,14 @@ __device__ __forceinline__ void rt_matvec(const double2 (&x)[4], int i0, int j, 
     e1 += dpp_f64<DPP_XOR1>(e1);
     if ((c & 1) == 0) {   // value 4 b3 + 2 b2 + b1: row q = 2 b3 + b2, part b1
         const int idx = (b3 ? 4 : 0) + (b2 ? 2 : 0) + (b1 ? 1 : 0);
-        atomicAdd(reinterpret_cast<double*>(p + i0 + (idx >> 1)) + (idx & 1), e1);
+        atomicAdd(reinterpret_cast<double*>(p + i0 + (idx >> 1)) + (idx & 1), quantize(e1, scale, inv_scale));
     }
     // column sums over the block's 4 row groups
     cs.x = swap_sum<true>(swap_sum<false>(cs.x));
     cs.y = swap_sum<true>(swap_sum<false>(cs.y));
     if (lane < 16 && j < n) {
-        atomicAdd(&p[j].x, cs.x);
-        atomicAdd(&p[j].y, cs.y);
+        atomicAdd(&p[j].x, quantize(cs.x, scale, inv_scale));
+        atomicAdd(&p[j].y, quantize(cs.y, scale, inv_scale));
     }
 }
 
@@ -353,6 +365,7 @@ __global__ void __launch_bounds__(RT_THREADS) tridiag_reg_kernel(const TriArgs a
     __shared__ double2 col[RT_N];
     __shared__ double2 sv[2][RT_N], sp[2][RT_N];
     __shared__ double2 s_tau;
+    __shared__ double fro2_w[RT_WAVES];
     // blocks RT_REG .. RT_BPW-1 of each wavefront: [wave][block][q][lane]
     __shared__ double2 AL[RT_WAVES * (RT_BPW - RT_REG) * 4 * 64];
     const int n = a.n, tid = threadIdx.x, lane = tid & 63;
@@ -365,6 +378,7 @@ __global__ void __launch_bounds__(RT_THREADS) tridiag_reg_kernel(const TriArgs a
     auto lds_blk = [&](int s, int q) -> double2& { return AL[((wv * (RT_BPW - RT_REG) + s - RT_REG) * 4 + q) * 64 + lane]; };
     int bI[RT_BPW], bJ[RT_BPW];
     double2 A[RT_REG][4];
+    double fro2 = 0.0;   // this lane's part of ||A||_F^2
 #pragma unroll
     for (int s = 0; s < RT_BPW; ++s) {
         rt_block(wv + RT_WAVES * s, nbr, bI[s], bJ[s]);
@@ -377,12 +391,23 @@ __global__ void __launch_bounds__(RT_THREADS) tridiag_reg_kernel(const TriArgs a
                 // Hermitian part of the input (the Gram is Hermitian up to its own rounding)
                 const double2 g = a.G[(size_t)i * n + j], gt = a.G[(size_t)j * n + i];
                 x = i == j ? make_double2(g.x, 0.0) : make_double2(0.5 * (g.x + gt.x), 0.5 * (g.y - gt.y));
+                fro2 += (i == j ? 1.0 : 2.0) * (x.x * x.x + x.y * x.y);
             }
             if (s < RT_REG) A[s][q] = x;
             else lds_blk(s, q) = x;
         }
     }
+    fro2 = wave_total(fro2);
+    if (lane == 0) fro2_w[wv] = fro2;
     __syncthreads();
+    // scale 2^(51 - e) with ||A||_F < 2^(e+1): partial sums of p_i below sqrt(2) 2^(e+1) + 13 delta
+    // < 2^52.6 delta
+    double fro = 0.0;
+#pragma unroll
+    for (int w = 0; w < RT_WAVES; ++w) fro += fro2_w[w];
+    fro = sqrt(fro);
+    const int fe = __builtin_amdgcn_readfirstlane(fro > 0.0 ? max(ilogb(fro), -900) : 0);
+    const double scale = ldexp(1.0, 51 - fe), inv_scale = ldexp(1.0, fe - 51);
     for (int k = 0; k < n - 1; ++k) {
         double2* v = sv[k & 1];
         double2* p = sp[k & 1];
@@ -438,12 +463,12 @@ __global__ void __launch_bounds__(RT_THREADS) tridiag_reg_kernel(const TriArgs a
             if (bI[s] < 0 || 16 * bJ[s] + 15 <= k) continue;
             const int j = 16 * bJ[s] + c, i0 = 16 * bI[s] + rb;
             if (s < RT_REG) {
-                rt_matvec(A[s < RT_REG ? s : 0], i0, j, n, c, lane, v, p);
+                rt_matvec(A[s < RT_REG ? s : 0], i0, j, n, c, lane, v, p, scale, inv_scale);
             } else {
                 double2 x[4];
 #pragma unroll
                 for (int q = 0; q < 4; ++q) x[q] = lds_blk(s, q);
-                rt_matvec(x, i0, j, n, c, lane, v, p);
+                rt_matvec(x, i0, j, n, c, lane, v, p, scale, inv_scale);
             }
         }
         __syncthreads();
