@@ -96,6 +96,25 @@ def test_gram_ragged_and_odd_voxel_counts(gpu, nv, nt):
         gpu.casorati_gram(x, G, ws, mode)
         assert rel_l2(G.cpu().numpy(), want) < 1e-6, mode
 
+
+@pytest.mark.parametrize('nt,bad', [(20, np.nan), (200, np.nan), (200, np.inf)])
+def test_non_finite_gram_reports_numeric_status(gpu, nt, bad):
+    """A Gram with a non-finite entry (the register-resident tridiagonalisation at 20 and 200
+    frames) is reported through the status word, not returned as a power-Doppler volume."""
+    import torch
+    NV = 3000
+    iq = random_casorati(NV, nt, seed=nt, rank=2).astype(np.complex64)
+    G = clutter.gram(iq)
+    G[3, 5] = G[5, 3] = bad
+    ws = torch.empty(gpu.svd_workspace_size(NV, nt), dtype=torch.uint8, device='cuda')
+    sigma = torch.empty(nt, dtype=torch.float64, device='cuda')
+    k = torch.zeros(1, dtype=torch.int32, device='cuda')
+    st = torch.full((1,), -1, dtype=torch.int32, device='cuda')
+    pd = torch.empty(NV, dtype=torch.float32, device='cuda')
+    gpu.svd_clutter_filter(dev(iq), dev(G), ws, sigma, k, -1, pd=pd, status=st)
+    assert int(st.item()) == 4   # FQ_E_NUMERIC
+    assert 1 <= int(k.item()) <= 64
+
 def test_full_cutoff_removes_everything(gpu):
     iq = random_casorati(2000, 12, seed=5).astype(np.complex64)
     out = gpu_svd_pd(dev(iq), 12)
