@@ -966,7 +966,8 @@ def main():
         c2 = workload_run(get_config('c2'), 3, 1, args, fq, torch, dev, filt, train, full=False)
         out['c2'] = {k: c2[k] for k in ('value', 'ms_per_step', 'config', 'rooflines', 'stage_ms', 'das_gunits_per_s',
                                        'pd_volumes_per_s', 'pd_volumes_per_s_two_in_flight',
-                                       'pd_volumes_per_s_in_step', 'learned_fallback', 'k_used',
+                                       'pd_volumes_per_s_graph', 'pd_volumes_per_s_in_step',
+                                       'learned_fallback', 'k_used',
                                        'eig_status', 'pd_error_db_vs_blood_truth', 'pd_rel_l2_vs_fp32_svd',
                                        'matched_error') if k in c2}
         out['c2']['steps'], out['c2']['warmup'] = 3, 1
