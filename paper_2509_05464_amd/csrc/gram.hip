@@ -365,9 +365,9 @@ Plan plan(int64_t nv, int nt, size_t max_bytes = 0) {
     p.nb = (nt + GT - 1) / GT;
     p.ntiles = p.nb * (p.nb + 1) / 2;
     group_tiles(p.nb, p);
-    // about 8192 workgroups (short voxel ranges: the groups of one range stay close enough
-    // in step to share its stages through the L2); ranges are whole multiples of 4096 voxels
-    int64_t want = std::max<int64_t>(1, 8192 / p.ngroups);
+    // about 16384 workgroups (short voxel ranges: the groups of one range stay close enough
+    // in step to share its stages through the L2); ranges are whole multiples of 2048 voxels
+    int64_t want = std::max<int64_t>(1, 16384 / p.ngroups);
     if (max_bytes) {
         // at most max_bytes of partial tiles: whole multiples of NXCD voxel ranges
         const size_t per_split = (size_t)p.ntiles * 2 * GT * GT * sizeof(double);
@@ -375,7 +375,7 @@ Plan plan(int64_t nv, int nt, size_t max_bytes = 0) {
         want = std::max<int64_t>(1, std::min<int64_t>(want, cap));
     }
     int64_t chunk = (nv + want - 1) / want;
-    chunk = std::max<int64_t>(4096, round_up((size_t)chunk, 4096));
+    chunk = std::max<int64_t>(2048, round_up((size_t)chunk, 2048));
     int64_t ns = (nv + chunk - 1) / chunk;
     p.nsplit = (int)round_up((size_t)ns, NXCD);
     p.chunk = chunk;
