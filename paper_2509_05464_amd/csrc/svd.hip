@@ -126,10 +126,11 @@ __global__ void __launch_bounds__(TRI_THREADS) tridiag_kernel(const TriArgs a) {
             if (sigma > 0.0 || alpha.y != 0.0) {
                 const double nrm = sqrt(alpha.x * alpha.x + alpha.y * alpha.y + sigma);
                 beta = alpha.x >= 0.0 ? -nrm : nrm;
-                tau = make_double2((beta - alpha.x) / beta, -alpha.y / beta);
+                const double ib = 1.0 / beta;
+                tau = make_double2((beta - alpha.x) * ib, -alpha.y * ib);
                 const double2 den = make_double2(alpha.x - beta, alpha.y);   // 1 / (alpha - beta)
-                const double dd = den.x * den.x + den.y * den.y;
-                scale = make_double2(den.x / dd, -den.y / dd);
+                const double idd = 1.0 / (den.x * den.x + den.y * den.y);
+                scale = make_double2(den.x * idd, -den.y * idd);
             }
             a.tau[k] = tau;
             a.e[k] = beta;
@@ -208,22 +209,25 @@ __global__ void __launch_bounds__(TRI_THREADS) tridiag_kernel(const TriArgs a) {
     }
 }
 
-// Register-resident form for n <= RT_N: the lower triangle of A (the Hermitian matrix) is
-// held in the registers of one workgroup for the whole reduction, so a step reads and
-// writes no global memory.  The triangle is cut into 16x16 blocks (I >= J), listed by
-// block column J descending and I ascending and dealt to the 8 wavefronts in turn (a
-// wavefront keeps blocks across the whole matrix, so the shrinking trailing block stays
-// spread over all of them); in a block, lane l holds rows 4(l/16) .. 4(l/16)+3 of column
-// l%16.  Step k:
+// Register-resident form for n <= RT_N: the lower block triangle of A (the Hermitian
+// matrix) is held in the registers of one workgroup for the whole reduction, so a step
+// reads and writes no global memory.  It is cut into 16x16 blocks (I >= J; the diagonal
+// blocks are held whole, both triangles), listed by block column J descending and I
+// ascending and dealt to the 8 wavefronts in turn (a wavefront keeps blocks across the
+// whole matrix, so the shrinking trailing block stays spread over all of them); in a
+// block, lane l holds rows 4(l/16) .. 4(l/16)+3 of column l%16.  Step k:
 //   1. the owners of column k put A[k..n-1][k] in LDS;
 //   2. one wavefront forms the reflector (same formulas as the kernel above);
-//   3. p = A22 v: each stored A_ij (i > j) adds A_ij v_j to p_i and conj(A_ij) v_i to p_j
-//      (the diagonal only the first): row sums are reduced over the block's 16 columns by
+//   3. p = A22 v: each stored A_ij adds A_ij v_j to p_i and, in the blocks below the
+//      diagonal, conj(A_ij) v_i to p_j: row sums are reduced over the block's 16 columns by
 //      a halving butterfly (each exchange halves the values a lane carries), column sums
 //      over its 4 row groups, both added into p with LDS atomics (each contribution rounded
 //      to a grid on which the FP64 sums are exact: the reduction is deterministic);
 //   4. every wavefront forms r = v^H p itself, and w = tau p - |tau|^2 r v / 2 on the fly;
-//   5. A22 -= v w^H + w v^H on the stored elements with j > k.
+//   5. A22 -= v w^H + w v^H on every stored element, with w_j taken as 0 in the columns
+//      j <= k already reduced (v_j = 0 there too, so they are left as they are).
+// Rows and columns past n start at zero and stay zero without a test: v is zero there, so
+// their p and w are zero and the update adds nothing.
 // v and p alternate between two buffers by step parity, so a step's writes never meet
 // the previous step's reads (three barriers per step).
 constexpr int RT_N = 208;                  // 13 block rows: 91 blocks, at most 12 per wavefront
@@ -298,7 +302,9 @@ __device__ __forceinline__ double quantize(double x, double scale, double inv_sc
     return rint(x * scale) * inv_scale;
 }
 
-// step 3 on one block (rows i0 .. i0+3 of column j in this lane)
+// step 3 on one block (rows i0 .. i0+3 of column j in this lane); a diagonal block holds
+// both triangles and adds its row sums only
+template <bool DIAG>
 __device__ __forceinline__ void rt_matvec(const double2 (&x)[4], int i0, int j, int n, int c, int lane,
                                           const double2* v, double2* p, double scale, double inv_scale) {
     const double2 vj = v[j];
@@ -309,7 +315,7 @@ __device__ __forceinline__ void rt_matvec(const double2 (&x)[4], int i0, int j, 
         const double2 r = zmul(x[q], vj);
         d[2 * q] = r.x;
         d[2 * q + 1] = r.y;
-        if (i0 + q > j) {
+        if (!DIAG) {
             const double2 t = zmul(zconj(x[q]), v[i0 + q]);
             cs.x += t.x;
             cs.y += t.y;
@@ -334,6 +340,7 @@ __device__ __forceinline__ void rt_matvec(const double2 (&x)[4], int i0, int j, 
         const int idx = (b3 ? 4 : 0) + (b2 ? 2 : 0) + (b1 ? 1 : 0);
         atomicAdd(reinterpret_cast<double*>(p + i0 + (idx >> 1)) + (idx & 1), quantize(e1, scale, inv_scale));
     }
+    if (DIAG) return;
     // column sums over the block's 4 row groups
     cs.x = swap_sum<true>(swap_sum<false>(cs.x));
     cs.y = swap_sum<true>(swap_sum<false>(cs.y));
@@ -344,20 +351,19 @@ __device__ __forceinline__ void rt_matvec(const double2 (&x)[4], int i0, int j, 
 }
 
 // step 5 on one block: A -= v w^H + w v^H, w = tau p - hw v, for this lane's stored elements
-__device__ __forceinline__ void rt_update(double2 (&x)[4], int i0, int j, int n, const double2* v, const double2* p,
+// (w_j = 0 in a column j <= k: p_j there holds partial sums of reduced columns, not A22 v)
+__device__ __forceinline__ void rt_update(double2 (&x)[4], int i0, int j, int k, const double2* v, const double2* p,
                                           double2 tau, double hw) {
     const double2 vj = v[j], tpj = zmul(tau, p[j]);
-    const double2 wj = make_double2(tpj.x - hw * vj.x, tpj.y - hw * vj.y);
+    const bool live = j > k;
+    const double2 wj = make_double2(live ? tpj.x - hw * vj.x : 0.0, live ? tpj.y - hw * vj.y : 0.0);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-        const int i = i0 + q;
-        if (i >= j && i < n) {
-            const double2 vi = v[i], tpi = zmul(tau, p[i]);
-            const double2 wi = make_double2(tpi.x - hw * vi.x, tpi.y - hw * vi.y);
-            const double2 u1 = zmulc(vi, wj), u2 = zmulc(wi, vj);
-            x[q].x -= u1.x + u2.x;
-            x[q].y -= u1.y + u2.y;
-        }
+        const double2 vi = v[i0 + q], tpi = zmul(tau, p[i0 + q]);
+        const double2 wi = make_double2(tpi.x - hw * vi.x, tpi.y - hw * vi.y);
+        const double2 u1 = zmulc(vi, wj), u2 = zmulc(wi, vj);
+        x[q].x -= u1.x + u2.x;
+        x[q].y -= u1.y + u2.y;
     }
 }
 
@@ -387,11 +393,11 @@ __global__ void __launch_bounds__(RT_THREADS) tridiag_reg_kernel(const TriArgs a
         for (int q = 0; q < 4; ++q) {
             const int i = 16 * bI[s] + rb + q;
             double2 x = make_double2(0.0, 0.0);
-            if (bI[s] >= 0 && i < n && j < n && i >= j) {
+            if (bI[s] >= 0 && i < n && j < n) {
                 // Hermitian part of the input (the Gram is Hermitian up to its own rounding)
                 const double2 g = a.G[(size_t)i * n + j], gt = a.G[(size_t)j * n + i];
                 x = i == j ? make_double2(g.x, 0.0) : make_double2(0.5 * (g.x + gt.x), 0.5 * (g.y - gt.y));
-                fro2 += (i == j ? 1.0 : 2.0) * (x.x * x.x + x.y * x.y);
+                fro2 += (bI[s] == bJ[s] ? 1.0 : 2.0) * (x.x * x.x + x.y * x.y);
             }
             if (s < RT_REG) A[s][q] = x;
             else lds_blk(s, q) = x;
@@ -436,10 +442,11 @@ __global__ void __launch_bounds__(RT_THREADS) tridiag_reg_kernel(const TriArgs a
             if (sigma > 0.0 || alpha.y != 0.0) {
                 const double nrm = sqrt(alpha.x * alpha.x + alpha.y * alpha.y + sigma);
                 beta = alpha.x >= 0.0 ? -nrm : nrm;
-                tau = make_double2((beta - alpha.x) / beta, -alpha.y / beta);
+                const double ib = 1.0 / beta;
+                tau = make_double2((beta - alpha.x) * ib, -alpha.y * ib);
                 const double2 den = make_double2(alpha.x - beta, alpha.y);   // 1 / (alpha - beta)
-                const double dd = den.x * den.x + den.y * den.y;
-                scale = make_double2(den.x / dd, -den.y / dd);
+                const double idd = 1.0 / (den.x * den.x + den.y * den.y);
+                scale = make_double2(den.x * idd, -den.y * idd);
             }
             if (lane == 0) {
                 a.tau[k] = tau;
@@ -463,12 +470,14 @@ __global__ void __launch_bounds__(RT_THREADS) tridiag_reg_kernel(const TriArgs a
             if (bI[s] < 0 || 16 * bJ[s] + 15 <= k) continue;
             const int j = 16 * bJ[s] + c, i0 = 16 * bI[s] + rb;
             if (s < RT_REG) {
-                rt_matvec(A[s < RT_REG ? s : 0], i0, j, n, c, lane, v, p, scale, inv_scale);
+                if (bI[s] == bJ[s]) rt_matvec<true>(A[s < RT_REG ? s : 0], i0, j, n, c, lane, v, p, scale, inv_scale);
+                else rt_matvec<false>(A[s < RT_REG ? s : 0], i0, j, n, c, lane, v, p, scale, inv_scale);
             } else {
                 double2 x[4];
 #pragma unroll
                 for (int q = 0; q < 4; ++q) x[q] = lds_blk(s, q);
-                rt_matvec(x, i0, j, n, c, lane, v, p, scale, inv_scale);
+                if (bI[s] == bJ[s]) rt_matvec<true>(x, i0, j, n, c, lane, v, p, scale, inv_scale);
+                else rt_matvec<false>(x, i0, j, n, c, lane, v, p, scale, inv_scale);
             }
         }
         __syncthreads();
@@ -482,14 +491,13 @@ __global__ void __launch_bounds__(RT_THREADS) tridiag_reg_kernel(const TriArgs a
         for (int s = 0; s < RT_BPW; ++s) {
             if (bI[s] < 0 || 16 * bJ[s] + 15 <= k) continue;
             const int j = 16 * bJ[s] + c, i0 = 16 * bI[s] + rb;
-            if (j <= k || j >= n) continue;
             if (s < RT_REG) {
-                rt_update(A[s < RT_REG ? s : 0], i0, j, n, v, p, tau, hw);
+                rt_update(A[s < RT_REG ? s : 0], i0, j, k, v, p, tau, hw);
             } else {
                 double2 x[4];
 #pragma unroll
                 for (int q = 0; q < 4; ++q) x[q] = lds_blk(s, q);
-                rt_update(x, i0, j, n, v, p, tau, hw);
+                rt_update(x, i0, j, k, v, p, tau, hw);
 #pragma unroll
                 for (int q = 0; q < 4; ++q) lds_blk(s, q) = x[q];
             }
