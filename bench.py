@@ -220,6 +220,49 @@ def das_only(cfg, args, fq, torch, dev):
                       'tflops': DAS_FLOP_PER_UNIT * units / (ms / 1e3) / 1e12}))
 
 
+def cu_split_streams(torch, n_small):
+    """Two streams at the default priority: one held to n_small CUs spread over the XCDs
+    (CU indices 0, 33, 66, ...), the other to the remaining CUs, by the HIP runtime's
+    CU-mask stream (the runtime torch itself loaded).  Falls back to two ordinary streams
+    if that call is not available; returns (streams, masked, release)."""
+    import ctypes
+    ncu = torch.cuda.get_device_properties(0).multi_processor_count
+    path = None
+    with open('/proc/self/maps') as f:
+        for line in f:
+            if 'libamdhip64' in line:
+                path = line.split()[-1]
+                break
+    try:
+        hip = ctypes.CDLL(path)
+        create = hip.hipExtStreamCreateWithCUMask
+        create.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_uint32, ctypes.POINTER(ctypes.c_uint32)]
+        destroy = hip.hipStreamDestroy
+        destroy.argtypes = [ctypes.c_void_p]
+    except (OSError, AttributeError, TypeError):
+        return (torch.cuda.Stream(), torch.cuda.Stream()), False, lambda: None
+    small = {(33 * i) % ncu for i in range(n_small)}
+    nw = (ncu + 31) // 32
+    handles = []
+    for members in (set(range(ncu)) - small, small):
+        words = [0] * nw
+        for c in members:
+            words[c // 32] |= 1 << (c % 32)
+        h = ctypes.c_void_p()
+        if create(ctypes.byref(h), nw, (ctypes.c_uint32 * nw)(*words)) != 0:
+            for x in handles:
+                destroy(x)
+            return (torch.cuda.Stream(), torch.cuda.Stream()), False, lambda: None
+        handles.append(h)
+
+    def release():
+        torch.cuda.synchronize()
+        for x in handles:
+            destroy(x)
+
+    return tuple(torch.cuda.ExternalStream(h.value) for h in handles), True, release
+
+
 def capture_graph(fn, torch):
     """fn (a clutter-filter path: kernel launches only, its size classes chosen on the device)
     captured once as a HIP graph, after one run on a side stream; replaying it drops the launch
@@ -683,11 +726,55 @@ def workload_run(cfg, steps, warmup, args, fq, torch, dev, filt, train, full=Tru
 
     out['pd_volumes_per_s_two_in_flight'] = {'svd_fp32': 1e3 / two_in_flight(fq.GRAM_FP32),
                                               'svd_split4_bf16': 1e3 / two_in_flight(fq.GRAM_SPLIT4_BF16)}
+
+    # a stream of ensembles, pipelined: the eigendecomposition and cutoff of volume v on a
+    # stream held to 8 CUs (one per XCD) while the other 248 form volume v+1's Gram and then
+    # volume v's projection and PD (svd_filter_apply); the eigensolver's single workgroup needs
+    # a whole CU, which a full-GPU Gram otherwise keeps taken
+    def pipelined(mode, streams, reps=8):
+        sets = [(G, gws, sws, sigma, k1, st1, pd_svd), (G2, gws2, sws2, sigma2, k2, st2, pd_split)]
+        M, E = streams
+
+        def run(n):
+            done = [None] * n
+            for v in range(n + 1):
+                if v < n:
+                    Gx, gx, sx, sg, kx, stx, pdx = sets[v % 2]
+                    g = torch.cuda.Event()
+                    with torch.cuda.stream(M):
+                        fq.casorati_gram(iq, Gx, gx, mode)
+                        g.record(M)
+                    with torch.cuda.stream(E):
+                        E.wait_event(g)
+                        fq.svd_clutter_filter(iq, Gx, sx, sg, kx, cfg.cutoff, status=stx)
+                        done[v] = torch.cuda.Event()
+                        done[v].record(E)
+                if v >= 1:
+                    Gx, gx, sx, sg, kx, stx, pdx = sets[(v - 1) % 2]
+                    with torch.cuda.stream(M):
+                        M.wait_event(done[v - 1])
+                        fq.svd_filter_apply(iq, sx, kx, pd=pdx)
+
+        run(2)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        run(reps)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / reps
+
+    pipe_streams, masked, release = cu_split_streams(torch, 8)
+    out['pd_volumes_per_s_pipelined'] = {'svd_fp32': 1e3 / pipelined(fq.GRAM_FP32, pipe_streams),
+                                         'svd_split4_bf16': 1e3 / pipelined(fq.GRAM_SPLIT4_BF16, pipe_streams),
+                                         'eig_cus': 8 if masked else None, 'cu_mask': masked}
+    release()
     out['pd_volumes_per_s_note'] = ('each path timed alone on one stream (mean of 5 after a warm-up): Gram + '
                                     'eigendecomposition + cutoff + fused projection and PD, or learned inference '
                                     'with PD; pd_volumes_per_s_two_in_flight: a stream of ensembles, the SVD path '
                                     'on two streams with volumes alternating (8 volumes, wall clock), one '
-                                    "volume's eigensolver beside the next one's Gram; pd_volumes_per_s_graph: the "
+                                    "volume's eigensolver beside the next one's Gram; pd_volumes_per_s_pipelined: "
+                                    'the same stream of ensembles with the eigendecomposition on a stream held to 8 '
+                                    'CUs and Gram + projection/PD (svd_filter_apply) on the other 248 (8 volumes, '
+                                    'wall clock); pd_volumes_per_s_graph: the '
                                     'SVD path captured once as a HIP graph and replayed (mean of 5); '
                                     'pd_volumes_per_s_in_step: the same stages inside the step, beside the other '
                                     'two filters')
@@ -965,7 +1052,7 @@ def main():
         # whole-step rate, per-stage times, filter paths and errors
         c2 = workload_run(get_config('c2'), 3, 1, args, fq, torch, dev, filt, train, full=False)
         out['c2'] = {k: c2[k] for k in ('value', 'ms_per_step', 'config', 'rooflines', 'stage_ms', 'das_gunits_per_s',
-                                       'pd_volumes_per_s', 'pd_volumes_per_s_two_in_flight',
+                                       'pd_volumes_per_s', 'pd_volumes_per_s_two_in_flight', 'pd_volumes_per_s_pipelined',
                                        'pd_volumes_per_s_graph', 'pd_volumes_per_s_in_step',
                                        'learned_fallback', 'k_used',
                                        'eig_status', 'pd_error_db_vs_blood_truth', 'pd_rel_l2_vs_fp32_svd',

@@ -264,6 +264,21 @@ int svd_clutter_filter(const float* iq, int64_t n_vox, int32_t n_t, const double
                        int32_t cutoff, void* ws, size_t ws_bytes, float* iq_filt, float* pd,
                        double* sigma, int32_t* k_used, int32_t* status, void* stream);
 
+/* svd_filter_apply -- the last stage of svd_clutter_filter alone (Section 2.4.2: S_f and
+ * the power Doppler above, same kernels, same results bit for bit), on the V_K and K that
+ * a svd_clutter_filter call on the same workspace left there (that call may pass NULL for
+ * iq_filt and pd: it then stops after the eigendecomposition and the cutoff).  It lets the
+ * eigendecomposition of one ensemble run on one stream while another stream forms the next
+ * ensemble's Gram; order the two calls with an event.
+ *  iq       complex64 [n_t][n_vox], the ensemble whose Gram was decomposed;
+ *  ws       the workspace of that call, unchanged since (n_t the same, ws_bytes at least
+ *           svd_workspace_size's figure without the SSM part);
+ *  k_used   int32 [1] (device), as written by that call;
+ *  iq_filt / pd  as above; at least one of them non-NULL (FQ_E_INVALID otherwise).
+ * Errors: FQ_E_INVALID for bad sizes or pointers, FQ_E_WORKSPACE for a short workspace. */
+int svd_filter_apply(const float* iq, int64_t n_vox, int32_t n_t, const void* ws, size_t ws_bytes,
+                     const int32_t* k_used, float* iq_filt, float* pd, void* stream);
+
 /* eigendecomposition only, every eigenvector (implicit QL with Wilkinson shifts on the
  * tridiagonal matrix, the rotations replayed on the identity): lam float64 [n_t]
  * descending (clamped >= 0), vecs complex128 [n_t][n_t] with column k the eigenvector of

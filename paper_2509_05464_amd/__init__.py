@@ -12,7 +12,7 @@ from ._lib import (  # noqa: F401
     Probe, Tx, Grid, Pulse, FdParams, make_probe, make_tx, make_grid, make_pulse, make_fd_params, lib,
     fd_workspace_size, fd_synth,
     rf_synth, das_workspace_size, das_window_rows, das_beamform, das_demodulate, das_delay_sum, gram_workspace_size, casorati_gram, casorati_gram_noalloc,
-    svd_workspace_size, svd_clutter_filter, hermitian_eig, power_doppler, ssm_workspace_size, spatial_similarity,
+    svd_workspace_size, svd_clutter_filter, svd_filter_apply, hermitian_eig, power_doppler, ssm_workspace_size, spatial_similarity,
     display_workspace_size, display_db, mip, image_quality,
     lcf_act_size, lcf_forward, lcf_backward, lcf_adam_step, lcf_gather,
     fallback_workspace_size, lcf_fallback,

@@ -117,6 +117,7 @@ _SIGS = {
     'casorati_gram_noalloc': (ctypes.c_int, [_vp, _i64, _i32, _i32, _vp, _vp]),
     'svd_workspace_size': (_sz, [_i64, _i32]),
     'svd_clutter_filter': (ctypes.c_int, [_vp, _i64, _i32, _vp, _i32, _vp, _sz, _vp, _vp, _vp, _vp, _vp, _vp]),
+    'svd_filter_apply': (ctypes.c_int, [_vp, _i64, _i32, _vp, _sz, _vp, _vp, _vp, _vp]),
     'hermitian_eig': (ctypes.c_int, [_vp, _i32, _vp, _sz, _vp, _vp, _vp, _vp]),
     'power_doppler': (ctypes.c_int, [_vp, _i64, _i32, _vp, _vp]),
     'ssm_workspace_size': (_sz, [_i64, _i32]),
@@ -297,6 +298,15 @@ def svd_clutter_filter(iq: torch.Tensor, gram: torch.Tensor, ws: torch.Tensor, s
                                   _ptr(_f32view(iq_filt)) if iq_filt is not None else None,
                                   _ptr(pd), _ptr(sigma), _ptr(k_used), _ptr(status), _stream())
     _check('svd_clutter_filter', st)
+
+
+def svd_filter_apply(iq: torch.Tensor, ws: torch.Tensor, k_used: torch.Tensor, iq_filt: Optional[torch.Tensor] = None,
+                     pd: Optional[torch.Tensor] = None) -> None:
+    """Projection and power Doppler from the V_K and K a svd_clutter_filter call left in ws."""
+    nt, nv = iq.shape
+    st = lib().svd_filter_apply(_ptr(_f32view(iq)), nv, nt, _ptr(ws), ws.numel() * ws.element_size(), _ptr(k_used),
+                                _ptr(_f32view(iq_filt)) if iq_filt is not None else None, _ptr(pd), _stream())
+    _check('svd_filter_apply', st)
 
 
 def hermitian_eig(gram: torch.Tensor, ws: torch.Tensor, lam: torch.Tensor, vecs: Optional[torch.Tensor] = None,

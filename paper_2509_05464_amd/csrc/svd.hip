@@ -1497,50 +1497,10 @@ extern "C" int hermitian_eig(const double* gram, int32_t n_t, void* ws, size_t w
     return launch_eig(gram, n_t, reinterpret_cast<char*>(ws), L, lam, nullptr, vecs, n_t, status, as_stream(stream));
 }
 
-extern "C" int svd_clutter_filter(const float* iq, int64_t n_vox, int32_t n_t, const double* gram, int32_t cutoff,
-                                  void* ws, size_t ws_bytes, float* iq_filt, float* pd, double* sigma,
-                                  int32_t* k_used, int32_t* status, void* stream) {
-    FQ_REQUIRE(n_t >= 1 && n_t <= FQ_MAX_NT, "n_t must be 1..%d", FQ_MAX_NT);
-    FQ_REQUIRE(n_vox >= 1, "n_vox must be >= 1");
-    FQ_REQUIRE(cutoff >= FQ_CUTOFF_SSM && cutoff <= n_t, "cutoff must be -2 (SSM), -1 (knee) or 0..n_t");
-    FQ_REQUIRE(cutoff != FQ_CUTOFF_SSM || n_t >= 2, "the SSM cutoff needs n_t >= 2");
-    FQ_REQUIRE(cutoff <= KMAX, "fixed cutoff above %d is not supported", KMAX);
-    FQ_REQUIRE(iq && gram && ws && sigma && k_used && aligned16(iq) && aligned16(gram) && aligned16(ws),
-               "null or misaligned pointer");
-    FQ_REQUIRE(!iq_filt || aligned16(iq_filt), "misaligned iq_filt");
-    const SvdWs L = svd_layout(n_t);
-    const size_t need = L.total + (cutoff == FQ_CUTOFF_SSM ? ssm_bytes(n_vox, n_t) : 0);
-    if (ws_bytes < need) {
-        set_error("workspace too small: %zu < %zu bytes", ws_bytes, need);
-        return FQ_E_WORKSPACE;
-    }
-    hipStream_t s = as_stream(stream);
-    char* w = reinterpret_cast<char*>(ws);
-    double* lam = reinterpret_cast<double*>(w + L.off_lam);
-    double* vecs = reinterpret_cast<double*>(w + L.off_vecs);
-    int st = launch_eigvals(gram, n_t, w, L, lam, sigma, status, s);
-    if (st != FQ_OK) return st;
-    RankArgs ra{lam, k_used, status, n_t, cutoff};
-    if (cutoff == FQ_CUTOFF_SSM) {
-        // the rank is read from the leading min(n_t, 64) spatial modes
-        const int M = std::min(n_t, FQ_SSM_MAX_MODES);
-        st = launch_eigvecs(n_t, w, L, nullptr, M, vecs, status, s);
-        if (st != FQ_OK) return st;
-        st = launch_ssm(iq, n_vox, n_t, vecs, M, w + L.total, nullptr, k_used, s);
-        if (st != FQ_OK) return st;
-        hipLaunchKernelGGL(rank_kernel, dim3(1), dim3(64), 0, s, ra);
-        FQ_LAUNCH_CHECK();
-    } else {
-        hipLaunchKernelGGL(rank_kernel, dim3(1), dim3(64), 0, s, ra);
-        FQ_LAUNCH_CHECK();
-        st = launch_eigvecs(n_t, w, L, k_used, 0, vecs, status, s);
-        if (st != FQ_OK) return st;
-    }
-    hipLaunchKernelGGL(vk_kernel, dim3((n_t * KMAX + 255) / 256), dim3(256), 0, s,
-                       reinterpret_cast<const double2*>(vecs), static_cast<const int*>(k_used),
-                       reinterpret_cast<float2*>(w + L.off_vk), reinterpret_cast<double2*>(w + L.off_vk64), n_t);
-    FQ_LAUNCH_CHECK();
-    if (!iq_filt && !pd) return FQ_OK;
+// The filter's last stage on the V_K (FP32 and FP64 copies) and K that the eigendecomposition
+// left in the workspace: the filtered IQ and/or the power Doppler.
+static int launch_apply(const float* iq, int64_t n_vox, int n_t, char* w, const SvdWs& L, int cutoff,
+                        const int32_t* k_used, float* iq_filt, float* pd, hipStream_t s) {
     PdArgs pa{};
     pa.iq = reinterpret_cast<const float2*>(iq);
     pa.vk = reinterpret_cast<const float2*>(w + L.off_vk);
@@ -1592,6 +1552,69 @@ extern "C" int svd_clutter_filter(const float* iq, int64_t n_vox, int32_t n_t, c
         }
     }
     return FQ_OK;
+}
+
+extern "C" int svd_clutter_filter(const float* iq, int64_t n_vox, int32_t n_t, const double* gram, int32_t cutoff,
+                                  void* ws, size_t ws_bytes, float* iq_filt, float* pd, double* sigma,
+                                  int32_t* k_used, int32_t* status, void* stream) {
+    FQ_REQUIRE(n_t >= 1 && n_t <= FQ_MAX_NT, "n_t must be 1..%d", FQ_MAX_NT);
+    FQ_REQUIRE(n_vox >= 1, "n_vox must be >= 1");
+    FQ_REQUIRE(cutoff >= FQ_CUTOFF_SSM && cutoff <= n_t, "cutoff must be -2 (SSM), -1 (knee) or 0..n_t");
+    FQ_REQUIRE(cutoff != FQ_CUTOFF_SSM || n_t >= 2, "the SSM cutoff needs n_t >= 2");
+    FQ_REQUIRE(cutoff <= KMAX, "fixed cutoff above %d is not supported", KMAX);
+    FQ_REQUIRE(iq && gram && ws && sigma && k_used && aligned16(iq) && aligned16(gram) && aligned16(ws),
+               "null or misaligned pointer");
+    FQ_REQUIRE(!iq_filt || aligned16(iq_filt), "misaligned iq_filt");
+    const SvdWs L = svd_layout(n_t);
+    const size_t need = L.total + (cutoff == FQ_CUTOFF_SSM ? ssm_bytes(n_vox, n_t) : 0);
+    if (ws_bytes < need) {
+        set_error("workspace too small: %zu < %zu bytes", ws_bytes, need);
+        return FQ_E_WORKSPACE;
+    }
+    hipStream_t s = as_stream(stream);
+    char* w = reinterpret_cast<char*>(ws);
+    double* lam = reinterpret_cast<double*>(w + L.off_lam);
+    double* vecs = reinterpret_cast<double*>(w + L.off_vecs);
+    int st = launch_eigvals(gram, n_t, w, L, lam, sigma, status, s);
+    if (st != FQ_OK) return st;
+    RankArgs ra{lam, k_used, status, n_t, cutoff};
+    if (cutoff == FQ_CUTOFF_SSM) {
+        // the rank is read from the leading min(n_t, 64) spatial modes
+        const int M = std::min(n_t, FQ_SSM_MAX_MODES);
+        st = launch_eigvecs(n_t, w, L, nullptr, M, vecs, status, s);
+        if (st != FQ_OK) return st;
+        st = launch_ssm(iq, n_vox, n_t, vecs, M, w + L.total, nullptr, k_used, s);
+        if (st != FQ_OK) return st;
+        hipLaunchKernelGGL(rank_kernel, dim3(1), dim3(64), 0, s, ra);
+        FQ_LAUNCH_CHECK();
+    } else {
+        hipLaunchKernelGGL(rank_kernel, dim3(1), dim3(64), 0, s, ra);
+        FQ_LAUNCH_CHECK();
+        st = launch_eigvecs(n_t, w, L, k_used, 0, vecs, status, s);
+        if (st != FQ_OK) return st;
+    }
+    hipLaunchKernelGGL(vk_kernel, dim3((n_t * KMAX + 255) / 256), dim3(256), 0, s,
+                       reinterpret_cast<const double2*>(vecs), static_cast<const int*>(k_used),
+                       reinterpret_cast<float2*>(w + L.off_vk), reinterpret_cast<double2*>(w + L.off_vk64), n_t);
+    FQ_LAUNCH_CHECK();
+    if (!iq_filt && !pd) return FQ_OK;
+    return launch_apply(iq, n_vox, n_t, w, L, cutoff, k_used, iq_filt, pd, s);
+}
+
+extern "C" int svd_filter_apply(const float* iq, int64_t n_vox, int32_t n_t, const void* ws, size_t ws_bytes,
+                                const int32_t* k_used, float* iq_filt, float* pd, void* stream) {
+    FQ_REQUIRE(n_t >= 1 && n_t <= FQ_MAX_NT, "n_t must be 1..%d", FQ_MAX_NT);
+    FQ_REQUIRE(n_vox >= 1, "n_vox must be >= 1");
+    FQ_REQUIRE(iq && ws && k_used && aligned16(iq) && aligned16(ws), "null or misaligned pointer");
+    FQ_REQUIRE(iq_filt || pd, "nothing to compute: iq_filt and pd are both null");
+    FQ_REQUIRE(!iq_filt || aligned16(iq_filt), "misaligned iq_filt");
+    const SvdWs L = svd_layout(n_t);
+    if (ws_bytes < L.total) {
+        set_error("workspace too small: %zu < %zu bytes", ws_bytes, L.total);
+        return FQ_E_WORKSPACE;
+    }
+    return launch_apply(iq, n_vox, n_t, reinterpret_cast<char*>(const_cast<void*>(ws)), L, -1, k_used, iq_filt, pd,
+                        as_stream(stream));
 }
 
 extern "C" int power_doppler(const float* iq, int64_t n_vox, int32_t n_t, float* pd, void* stream) {

@@ -118,6 +118,8 @@ def test_invalid_arguments_return_status(lib):
     assert st == 1 and b'n_t' in L.fq_last_error()
     st = L.svd_clutter_filter(None, 10, 20, None, -3, None, 0, None, None, None, None, None, None)
     assert st == 1 and b'cutoff' in L.fq_last_error()
+    st = L.svd_filter_apply(None, 10, 600, None, 0, None, None, None, None)
+    assert st == 1 and b'n_t' in L.fq_last_error()
     st = L.spatial_similarity(None, 10, 20, None, 1, None, 0, None, None, None)
     assert st == 1 and b'n_modes' in L.fq_last_error()
     st = L.spatial_similarity(None, 10, 20, None, 21, None, 0, None, None, None)

@@ -173,3 +173,43 @@ def test_rf_synth_pulse_lengths(gpu, n_cycles, trunc):
     err = rel_l2(rf.cpu().numpy().reshape(sel.shape[0], -1), want)
     print('pulse', n_cycles, trunc, 'rf rel L2', err)
     assert err < 2e-5
+
+
+@pytest.mark.parametrize('nt,cutoff', [(200, -1), (64, 20), (33, 3)])
+def test_filter_apply_after_eig_equals_one_call(gpu, nt, cutoff):
+    """The filter's last stage run by svd_filter_apply on a second stream, after a
+    svd_clutter_filter call that stops at the cutoff, gives what one svd_clutter_filter
+    call gives, bit for bit (filtered IQ and PD; PD alone too)."""
+    import torch
+    nv = 40000
+    print('filter apply n_t', nt, 'cutoff', cutoff, flush=True)
+    iq = dev(random_casorati(nv, nt, seed=300 + nt, rank=3).astype(np.complex64))
+    G = torch.empty((nt, nt), dtype=torch.complex128, device='cuda')
+    gws = torch.empty(gpu.gram_workspace_size(nv, nt, 0), dtype=torch.uint8, device='cuda')
+    gpu.casorati_gram(iq, G, gws, 0)
+
+    def run(ws, **out):
+        sigma = torch.empty(nt, dtype=torch.float64, device='cuda')
+        k = torch.zeros(1, dtype=torch.int32, device='cuda')
+        st = torch.full((1,), -1, dtype=torch.int32, device='cuda')
+        gpu.svd_clutter_filter(iq, G, ws, sigma, k, cutoff, status=st, **out)
+        return k, st
+
+    ws1 = torch.empty(gpu.svd_workspace_size(nv, nt), dtype=torch.uint8, device='cuda')
+    ws2 = torch.empty_like(ws1)
+    iqf1, pd1, pd1b = torch.empty_like(iq), torch.empty(nv, device='cuda'), torch.empty(nv, device='cuda')
+    k1, st1 = run(ws1, iq_filt=iqf1, pd=pd1)
+    run(ws1, pd=pd1b)
+    k2, st2 = run(ws2)
+    done = torch.cuda.Event()
+    done.record()
+    side = torch.cuda.Stream()
+    iqf2, pd2, pd2b = torch.empty_like(iq), torch.empty(nv, device='cuda'), torch.empty(nv, device='cuda')
+    with torch.cuda.stream(side):
+        side.wait_event(done)
+        gpu.svd_filter_apply(iq, ws2, k2, iq_filt=iqf2, pd=pd2)
+        gpu.svd_filter_apply(iq, ws2, k2, pd=pd2b)
+    torch.cuda.synchronize()
+    assert int(st1.item()) == 0 and int(st2.item()) == 0
+    assert int(k1.item()) == int(k2.item())
+    assert torch.equal(iqf1, iqf2) and torch.equal(pd1, pd2) and torch.equal(pd1b, pd2b)
