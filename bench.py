@@ -762,10 +762,16 @@ def workload_run(cfg, steps, warmup, args, fq, torch, dev, filt, train, full=Tru
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) * 1e3 / reps
 
+    # (every kernel of the path has run on the default stream above before the masked streams
+    # are made; a failure here is reported in the line instead of ending the run)
     pipe_streams, masked, release = cu_split_streams(torch, 8)
-    out['pd_volumes_per_s_pipelined'] = {'svd_fp32': 1e3 / pipelined(fq.GRAM_FP32, pipe_streams),
-                                         'svd_split4_bf16': 1e3 / pipelined(fq.GRAM_SPLIT4_BF16, pipe_streams),
-                                         'eig_cus': 8 if masked else None, 'cu_mask': masked}
+    try:
+        out['pd_volumes_per_s_pipelined'] = {'svd_fp32': 1e3 / pipelined(fq.GRAM_FP32, pipe_streams),
+                                             'svd_split4_bf16': 1e3 / pipelined(fq.GRAM_SPLIT4_BF16, pipe_streams),
+                                             'eig_cus': 8 if masked else None, 'cu_mask': masked}
+    except fq.FqError as e:
+        torch.cuda.synchronize()
+        out['pd_volumes_per_s_pipelined'] = {'error': str(e), 'cu_mask': masked}
     release()
     out['pd_volumes_per_s_note'] = ('each path timed alone on one stream (mean of 5 after a warm-up): Gram + '
                                     'eigendecomposition + cutoff + fused projection and PD, or learned inference '
