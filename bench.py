@@ -220,11 +220,23 @@ def das_only(cfg, args, fq, torch, dev):
                       'tflops': DAS_FLOP_PER_UNIT * units / (ms / 1e3) / 1e12}))
 
 
+_CU_SPLIT = {}
+
+
 def cu_split_streams(torch, n_small):
     """Two streams at the default priority: one held to n_small CUs spread over the XCDs
     (CU indices 0, 33, 66, ...), the other to the remaining CUs, by the HIP runtime's
     CU-mask stream (the runtime torch itself loaded).  Falls back to two ordinary streams
-    if that call is not available; returns (streams, masked, release)."""
+    if that call is not available; returns (streams, masked, release).  The pair is made
+    once per process and kept to its end (making a second pair after destroying the first
+    has failed its first launch)."""
+    if n_small not in _CU_SPLIT:
+        _CU_SPLIT[n_small] = _make_cu_split(torch, n_small)
+    streams, masked = _CU_SPLIT[n_small]
+    return streams, masked, torch.cuda.synchronize
+
+
+def _make_cu_split(torch, n_small):
     import ctypes
     ncu = torch.cuda.get_device_properties(0).multi_processor_count
     path = None
@@ -240,7 +252,7 @@ def cu_split_streams(torch, n_small):
         destroy = hip.hipStreamDestroy
         destroy.argtypes = [ctypes.c_void_p]
     except (OSError, AttributeError, TypeError):
-        return (torch.cuda.Stream(), torch.cuda.Stream()), False, lambda: None
+        return (torch.cuda.Stream(), torch.cuda.Stream()), False
     small = {(33 * i) % ncu for i in range(n_small)}
     nw = (ncu + 31) // 32
     handles = []
@@ -252,15 +264,9 @@ def cu_split_streams(torch, n_small):
         if create(ctypes.byref(h), nw, (ctypes.c_uint32 * nw)(*words)) != 0:
             for x in handles:
                 destroy(x)
-            return (torch.cuda.Stream(), torch.cuda.Stream()), False, lambda: None
+            return (torch.cuda.Stream(), torch.cuda.Stream()), False
         handles.append(h)
-
-    def release():
-        torch.cuda.synchronize()
-        for x in handles:
-            destroy(x)
-
-    return tuple(torch.cuda.ExternalStream(h.value) for h in handles), True, release
+    return tuple(torch.cuda.ExternalStream(h.value) for h in handles), True
 
 
 def capture_graph(fn, torch):
